@@ -1,0 +1,223 @@
+/*
+ * alofdft.h -- C ABI of the MI355X (gfx950) implementation of the augmented
+ * Lagrangian orbital-free DFT ground-state solve of Suryanarayana & Phanish,
+ * "Augmented Lagrangian formulation of Orbital-Free Density Functional Theory"
+ * (arXiv:1405.6456).
+ *
+ * Problem statement (Sec. 2 and Sec. 4): M nuclei with positions R and valence
+ * charges Z on a uniform grid of spacing h; the electron density is u^2 with
+ * u >= 0, and the energy is the TFW kinetic energy (Eq. KineticEnergy), LDA
+ * exchange-correlation, and the electrostatics rewritten through the potential
+ * phi of the charge u^2 + b (Eq. ElectroststaticReformulation).  The ground state
+ * minimises the energy subject to h^3 sum u^2 = N (the constraint C_h of Sec. 4),
+ * solved by the augmented Lagrangian iteration (Sec. 3, Algorithm AugLag) around a
+ * Polak-Ribiere nonlinear CG inner solver (Sec. 4); phi is re-solved for every
+ * update of u (Eq. Poisson:Discretized, here by conjugate gradients).  Forces are
+ * the Hellmann-Feynman expression of Eq. Force:Nuclei with the order-2n FD
+ * gradient, plus the overlap correction of Appendix A.
+ *
+ * Conventions for every call:
+ *   - Atomic units (Hartree, Bohr).
+ *   - Grid arrays are dense n[0]*n[1]*n[2] doubles, node (i,j,k) at
+ *     origin + h*(i,j,k), flat index i + n[0]*(j + n[1]*k) (x fastest).
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP device
+ *     memory on the context's device (for example a torch tensor's data_ptr()).
+ *   - The caller owns every input and output buffer; the library owns only the
+ *     context (and server) workspace.  Outputs are complete when a call returns.
+ *   - Every call returns an int status: ALOFDFT_OK (0), ALOFDFT_NOT_CONVERGED (1,
+ *     outputs hold the last iterate), ALOFDFT_PENDING (2) or a negative error.
+ *     No exception or exit crosses the ABI; alofdft_last_error() gives detail.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef ALOFDFT_H
+#define ALOFDFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ALOFDFT_OK 0
+#define ALOFDFT_NOT_CONVERGED 1
+#define ALOFDFT_PENDING 2
+#define ALOFDFT_INVALID_ARGUMENT (-1)
+#define ALOFDFT_OUT_OF_MEMORY (-2)
+#define ALOFDFT_DEVICE_ERROR (-3)
+#define ALOFDFT_NUMERICAL (-4)
+#define ALOFDFT_REJECTED (-5)
+
+/* constraint methods (Sec. 3; Sec. 5.3.2 for the two comparison methods) */
+#define ALOFDFT_METHOD_AUGMENTED_LAGRANGIAN 0
+#define ALOFDFT_METHOD_PENALTY 1
+
+/* boundary values of phi: zero Dirichlet (Sec. 4) or the multipole expansion
+ * (monopole + dipole + traceless quadrupole of u^2 + b about the box centre)
+ * suggested in Sec. 5.1 */
+#define ALOFDFT_BC_ZERO 0
+#define ALOFDFT_BC_MULTIPOLE 1
+
+/* arithmetic of the Poisson solve: all FP64, or FP32 stencil and CG vectors
+ * inside an FP64 iterative-refinement loop (FP64 residual, dots, phi) */
+#define ALOFDFT_FP64 0
+#define ALOFDFT_FP32_REFINED 1
+
+#define ALOFDFT_XC_NONE 0
+#define ALOFDFT_XC_LDA_PZ 1
+
+typedef struct alofdft_ctx alofdft_ctx;
+
+typedef struct {
+  int fd_half_width;      /* n of the order-2n stencils, 1..8 (default 6: order 12) */
+  double lambda;          /* von Weizsaecker weight (default 0.2, Sec. 5) */
+  int xc;                 /* ALOFDFT_XC_* (default LDA_PZ, Sec. 2) */
+  double gauss_width;     /* s of b_J = -Z pi^-3/2 s^-3 exp(-r^2/s^2) (default 1.0) */
+  double r_cut;           /* support radius of b_J (default 7.0) */
+  int method;             /* ALOFDFT_METHOD_* (default augmented Lagrangian) */
+  double eta0, mu0, kappa; /* Algorithm AugLag inputs (defaults -0.2, 1.0, 0.1, Sec. 5.3.1) */
+  double tol_constraint;  /* stop the outer loop at |C_h|/N below this (1e-8) */
+  double tol_grad;        /* inner stop: (h^3 sum g^2)^1/2 below this (1e-6) */
+  double tol_poisson;     /* ||rhs - A phi||_2 / ||rhs||_2 below this (1e-10) */
+  int phi_bc;             /* ALOFDFT_BC_* (default multipole) */
+  int precision;          /* ALOFDFT_FP64 or ALOFDFT_FP32_REFINED */
+  int max_outer;          /* outer (multiplier) iterations (30) */
+  int max_inner;          /* nonlinear CG iterations per outer step (20000) */
+  int max_cg;             /* CG iterations per Poisson solve (100000) */
+  double sigma0;          /* secant probe step (0.5) */
+  int max_secant;         /* secant steps per line search (4) */
+  double secant_rel;      /* line-search slope reduction (0.1) */
+  int restart_every;      /* nonlinear CG restart period (50) */
+  int cg_check_every;     /* CG iterations between host convergence checks (16) */
+  uint64_t seed;          /* seed of the default initial guess (6456) */
+} alofdft_params;
+
+typedef struct {
+  int M;                  /* number of atoms, >= 1 */
+  const double* R;        /* host, 3*M positions */
+  const double* Z;        /* host, M charges */
+  double N_elec;          /* number of electrons, > 0 */
+  int n[3];               /* nodes per axis, each >= 2*fd_half_width+1 */
+  double h;               /* grid spacing, > 0 */
+  double origin[3];       /* position of node (0,0,0) */
+} alofdft_system;
+
+typedef struct {
+  long long outer, inner, grad_evals, poisson_solves, cg_iters;
+  long long matvec_fp64, matvec_fp32; /* stencil applications per precision */
+  long long refinements;              /* FP64 outer residuals of the refined solve */
+} alofdft_counts;
+
+typedef struct {
+  double E_total, E_TF, E_vW, E_xc, E_es, E_self, E_corr; /* Hartree */
+  double eta_star;        /* Lagrange multiplier estimate (Algorithm AugLag output) */
+  double C_h;             /* h^3 sum u^2 - N at the returned u */
+  double grad_norm;       /* (h^3 sum g^2)^1/2 at the returned u */
+  double poisson_relres;  /* relative residual of the last Poisson solve */
+  double dE_last;         /* energy change of the last outer step */
+  alofdft_counts counts;
+  double time_total_ms, time_poisson_ms, time_grad_ms, time_setup_ms;
+  int status;
+} alofdft_result;
+
+typedef struct {
+  double E_TF, E_vW, E_xc, E_es, E_self, E_corr, E_total; /* Hartree */
+  double C_h;             /* h^3 sum u^2 - N */
+  double L;               /* E - eta C_h + C_h^2/(2 mu) */
+  double grad_norm;       /* (h^3 sum g^2)^1/2 */
+  long long cg_iters;
+} alofdft_energy;
+
+/* Status text for a return code. */
+const char* alofdft_strerror(int status);
+
+/* Detail of the last error on this context (never NULL). */
+const char* alofdft_last_error(const alofdft_ctx* ctx);
+
+/* Fills *p with the defaults listed above.  Returns ALOFDFT_OK or INVALID_ARGUMENT. */
+int alofdft_default_params(alofdft_params* p);
+
+/* Creates a context on HIP device `hip_device` that enqueues all work on
+ * `hip_stream` (a hipStream_t, borrowed, may be NULL for the null stream).  The
+ * context allocates its device workspace lazily and owns it until destroy. */
+int alofdft_create(alofdft_ctx** out, int hip_device, void* hip_stream);
+void alofdft_destroy(alofdft_ctx* ctx);
+
+/* Ground state for fixed nuclei (Sec. 3, Algorithm AugLag; method = penalty
+ * runs the same loop with eta fixed at 0, Sec. 5.3.2).
+ *   u0         host, grid array, nullable: NULL uses sqrt(N/V)(1 + 0.05 xi),
+ *              xi uniform in [-1,1) from SplitMix64(seed XOR node index).
+ *   u_out, phi_out  host grid arrays, nullable.
+ *   forces_out host 3*M, nullable: Hellmann-Feynman forces (Eq. Force:Nuclei,
+ *              FD gradient of Sec. 4) plus the Appendix-A overlap correction.
+ *   res        required.
+ * Errors: INVALID_ARGUMENT for h <= 0, fd_half_width outside 1..8, n < 2n+1,
+ * M < 1, N <= 0, an atom whose r_cut ball leaves the box, non-finite input;
+ * OUT_OF_MEMORY; DEVICE_ERROR; NUMERICAL when a non-finite value appears. */
+int alofdft_solve(alofdft_ctx* ctx, const alofdft_system* sys, const alofdft_params* prm, const double* u0,
+                  double* u_out, double* phi_out, double* forces_out, alofdft_result* res);
+
+/* Same as alofdft_solve with device grid arrays (u0_dev nullable, u_out_dev and
+ * phi_out_dev nullable) and host forces; all device work is ordered on the
+ * context stream and complete on return. */
+int alofdft_solve_device(alofdft_ctx* ctx, const alofdft_system* sys, const alofdft_params* prm,
+                         const double* u0_dev, double* u_out_dev, double* phi_out_dev, double* forces_out,
+                         alofdft_result* res);
+
+/* y = Delta_h x, the order-2*fd_half_width stencil of Eq. FD:Laplacian with zero
+ * ghosts.  x_dev, y_dev: device grid arrays of n[0]*n[1]*n[2] elements of type
+ * dtype (0 = double, 1 = float).  Returns INVALID_ARGUMENT for bad sizes. */
+int alofdft_apply_laplacian(alofdft_ctx* ctx, const int n[3], double h, int fd_half_width, int dtype,
+                            const void* x_dev, void* y_dev);
+
+/* Discrete Poisson problem -(1/4pi) Delta_h phi = rho (Eq. Poisson:Discretized)
+ * with boundary values `bc` (ALOFDFT_BC_*), solved by conjugate gradients in
+ * `precision` (ALOFDFT_FP64 / FP32_REFINED) from the guess in phi_dev to
+ * ||rhs - A phi||_2 < tol ||rhs||_2.  rho_dev, phi_dev: device grid arrays.
+ * *iters (nullable) receives the CG iterations; *relres (nullable) the final
+ * relative residual.  NOT_CONVERGED at max_cg. */
+int alofdft_poisson(alofdft_ctx* ctx, const int n[3], double h, const double origin[3], int fd_half_width,
+                    int bc, int precision, const double* rho_dev, double* phi_dev, double tol, int max_cg,
+                    long long* iters, double* relres);
+
+/* One energy and residual evaluation at u (Sec. 2 Eq. F with the quadrature of
+ * Sec. 4; residual of Eq. EulerLagrangeDiscretized):
+ *   g = -(lambda/2) Delta_h u + (V_K + V_xc + phi) u + (-eta + C_h/mu) u
+ * (mu <= 0 drops the C_h/mu term).  phi_dev is the warm start on entry and the
+ * potential of u on return.  u_dev, phi_dev, g_dev (nullable): device grid
+ * arrays.  e: required. */
+int alofdft_energy_gradient(alofdft_ctx* ctx, const alofdft_system* sys, const alofdft_params* prm,
+                            const double* u_dev, double eta, double mu, double* phi_dev, double* g_dev,
+                            alofdft_energy* e);
+
+/* Nuclear pseudocharge b = sum_J b_J on the grid (Sec. 4 construction, Gaussian
+ * b_J with support r_cut).  b_dev: device grid array.  *self_energy (nullable)
+ * receives 1/2 sum_J h^3 sum b_J V_J. */
+int alofdft_pseudocharge(alofdft_ctx* ctx, const alofdft_system* sys, const alofdft_params* prm, double* b_dev,
+                         double* self_energy);
+
+/* Forces for a given potential (Eq. Force:Nuclei with the order-2n FD gradient
+ * of b_J, plus the Appendix-A correction).  phi_dev: device grid array;
+ * forces_out: host 3*M. */
+int alofdft_forces(alofdft_ctx* ctx, const alofdft_system* sys, const alofdft_params* prm, const double* phi_dev,
+                   double* forces_out);
+
+/* Stencil throughput measurement: applies Delta_h `reps` times over a rotation
+ * of `nbuf` distinct (x, y) padded array pairs of n^3 elements (dtype 0/1) and
+ * returns the mean kernel time per application in *ms_per_apply (HIP events on
+ * the context stream).  Inputs are filled with a fixed pattern. */
+int alofdft_bench_stencil(alofdft_ctx* ctx, const int n[3], int fd_half_width, int dtype, int reps, int nbuf,
+                          double* ms_per_apply);
+
+/* Launch tuning of a context: stencil tile variant (0..4: 64x8, 64x16, 32x16,
+ * 64x8 with one row per thread, 64x8 with four rows per thread; x by y, in
+ * nodes, for the order-12 stencil), the target number of stencil workgroups
+ * (z chunking), and the FP32 inner-solve residual reduction 10^-inner_tol_exp
+ * of the refined Poisson solve (1..7).  Defaults 3, 1024, 4.  INVALID_ARGUMENT
+ * outside those ranges. */
+int alofdft_set_tuning(alofdft_ctx* ctx, int stencil_variant, int target_blocks, int inner_tol_exp);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ALOFDFT_H */

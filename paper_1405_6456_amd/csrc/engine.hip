@@ -1,0 +1,1243 @@
+// Host engine and C ABI of the MI355X AL orbital-free DFT solve.
+//
+// The host owns control flow only: the augmented Lagrangian / penalty outer
+// loop (Sec. 3, Algorithm AugLag; Sec. 5.3.2), the nonlinear CG line-search
+// logic (Sec. 4) and convergence tests.  Every grid-sized step runs in the gfx950
+// kernels of kernels.hip; the Poisson CG keeps its scalars on the device and the
+// host only polls its done flag every cg_check_every iterations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/alofdft.h"
+#include "common.h"
+#include "kernels.hip"
+
+using namespace alofdft;
+
+struct alofdft_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::map<std::string, std::pair<void*, size_t>> bufs;
+  double* pin = nullptr;  // pinned host scalars
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  int variant = 3;        // stencil tile variant
+  int target_blocks = 1024;
+  int inner_tol_exp = 4;  // FP32 inner CG reduces the residual by 10^-inner_tol_exp
+  // geometry each padded work array was last zeroed for (its halo is zero only then)
+  std::map<std::string, std::string> geom_key;
+};
+
+namespace {
+
+// ----------------------------------------------------------------- errors
+struct Fail {
+  int code;
+};
+
+void set_err(alofdft_ctx* c, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+}
+
+#define HIPC(c, x)                                                              \
+  do {                                                                          \
+    hipError_t e_ = (x);                                                        \
+    if (e_ != hipSuccess) {                                                     \
+      set_err(c, "%s failed: %s (%s:%d)", #x, hipGetErrorString(e_), __FILE__, __LINE__); \
+      throw Fail{e_ == hipErrorOutOfMemory ? ALOFDFT_OUT_OF_MEMORY : ALOFDFT_DEVICE_ERROR}; \
+    }                                                                           \
+  } while (0)
+
+#define CHECK_LAUNCH(c) HIPC(c, hipGetLastError())
+
+void require(alofdft_ctx* c, bool ok, const char* msg) {
+  if (!ok) {
+    set_err(c, "%s", msg);
+    throw Fail{ALOFDFT_INVALID_ARGUMENT};
+  }
+}
+
+// ----------------------------------------------------------------- buffers
+void* buf(alofdft_ctx* c, const std::string& name, size_t bytes) {
+  auto it = c->bufs.find(name);
+  if (it != c->bufs.end()) {
+    if (it->second.second >= bytes) return it->second.first;
+    HIPC(c, hipFree(it->second.first));
+    c->bufs.erase(it);
+  }
+  void* p = nullptr;
+  HIPC(c, hipMalloc(&p, bytes));
+  HIPC(c, hipMemsetAsync(p, 0, bytes, c->stream));
+  c->bufs[name] = {p, bytes};
+  return p;
+}
+template <typename T>
+T* bufT(alofdft_ctx* c, const std::string& name, size_t count) {
+  return (T*)buf(c, name, count * sizeof(T));
+}
+
+void sync(alofdft_ctx* c) { HIPC(c, hipStreamSynchronize(c->stream)); }
+
+// ----------------------------------------------------------------- layout and weights
+int roundup(int a, int b) { return (a + b - 1) / b * b; }
+
+Geom make_geom(const int n[3], int R) {
+  Geom g;
+  g.nx = n[0];
+  g.ny = n[1];
+  g.nz = n[2];
+  g.R = R;
+  const int ox = 16;  // >= R, keeps interior rows 64-byte aligned for float and double
+  g.px = roundup(ox + roundup(n[0], 64) + R, 16);
+  g.py = R + roundup(n[1], 32) + R;
+  g.pz = n[2] + 2 * R;
+  g.plane = (long long)g.px * g.py;
+  g.base = (long long)R * g.plane + (long long)R * g.px + ox;
+  g.total = g.plane * g.pz;
+  return g;
+}
+
+// Laplacian weights of Eq. FD:Laplacian: w_0 = -(1/h^2) sum_q 1/q^2,
+// w_p = 2(-1)^(p+1)/(h^2 p^2) (n!)^2/((n-p)!(n+p)!).
+void lap_weights(int n, double h, double* w) {
+  double s = 0.0;
+  for (int q = 1; q <= n; ++q) s += 1.0 / (double(q) * q);
+  w[0] = -s / (h * h);
+  double ratio = 1.0;
+  for (int p = 1; p <= n; ++p) {
+    ratio *= double(n - p + 1) / double(n + p);
+    w[p] = ((p & 1) ? 2.0 : -2.0) / (h * h * p * p) * ratio;
+  }
+}
+// Gradient weights of Sec. 4: w~_p = (-1)^(p+1)/(h p) (n!)^2/((n-p)!(n+p)!).
+void grad_weights(int n, double h, double* w) {
+  w[0] = 0.0;
+  double ratio = 1.0;
+  for (int p = 1; p <= n; ++p) {
+    ratio *= double(n - p + 1) / double(n + p);
+    w[p] = ((p & 1) ? 1.0 : -1.0) / (h * p) * ratio;
+  }
+}
+template <typename T>
+StencilW<T> stencil_weights(int n, double h, double scale) {
+  double w[kMaxRadius + 1];
+  lap_weights(n, h, w);
+  StencilW<T> W;
+  W.c0 = (T)(6.0 * w[0] * scale);
+  for (int p = 0; p <= kMaxRadius; ++p) W.w[p] = (T)(p <= n && p > 0 ? w[p] * scale : 0.0);
+  return W;
+}
+
+// ----------------------------------------------------------------- launches
+int pw_blocks(const Geom& g) {
+  const int rows = g.ny * g.nz;
+  const int waves_per_block = kPointwiseThreads / 64;
+  return std::max(1, std::min(kPointwiseBlocks, (rows + waves_per_block - 1) / waves_per_block));
+}
+
+template <class Op>
+int launch_pw(alofdft_ctx* c, const Geom& g, const Op& op) {
+  const int nb = pw_blocks(g);
+  hipLaunchKernelGGL((k_pointwise<Op, kPointwiseThreads>), dim3(nb), dim3(kPointwiseThreads), 0, c->stream, g, op);
+  CHECK_LAUNCH(c);
+  return nb;
+}
+
+template <typename T, int R, int BX, int BY, int VY, class Op>
+int launch_cfg(alofdft_ctx* c, const Geom& g, const StencilW<T>& W, const Op& op) {
+  const int tiles_x = (g.nx + BX - 1) / BX;
+  const int tiles_y = (g.ny + BY * VY - 1) / (BY * VY);
+  const int tiles = tiles_x * tiles_y;
+  int nchunks = std::max(1, (c->target_blocks + tiles - 1) / tiles);
+  int zc = std::max((g.nz + nchunks - 1) / nchunks, std::min(g.nz, 2 * R + 2));
+  nchunks = (g.nz + zc - 1) / zc;
+  const int nb = tiles * nchunks;
+  hipLaunchKernelGGL((k_stencil<T, R, BX, BY, VY, Op>), dim3(nb), dim3(BX * BY), 0, c->stream, g, W, zc, tiles_x,
+                     tiles_y, op);
+  CHECK_LAUNCH(c);
+  return nb;
+}
+
+// Largest number of blocks any stencil launch can use (partials buffers are sized by it).
+int max_stencil_blocks(const Geom& g, int target) {
+  const int tiles = ((g.nx + 31) / 32) * ((g.ny + 7) / 8);
+  return tiles * std::max(1, (target + tiles - 1) / tiles) + tiles * 4 + 64;
+}
+
+template <typename T, int R, class Op>
+int launch_r(alofdft_ctx* c, const Geom& g, const StencilW<T>& W, const Op& op) {
+  if constexpr (R == 6) {
+    switch (c->variant) {
+      case 1: return launch_cfg<T, R, 64, 4, 4, Op>(c, g, W, op);
+      case 2: return launch_cfg<T, R, 32, 8, 2, Op>(c, g, W, op);
+      case 3: return launch_cfg<T, R, 64, 8, 1, Op>(c, g, W, op);
+      case 4: return launch_cfg<T, R, 64, 2, 4, Op>(c, g, W, op);
+      default: break;
+    }
+  }
+  return launch_cfg<T, R, 64, 4, 2, Op>(c, g, W, op);
+}
+
+template <typename T, class Op>
+int launch_stencil(alofdft_ctx* c, const Geom& g, const StencilW<T>& W, const Op& op) {
+  switch (g.R) {
+    case 1: return launch_r<T, 1>(c, g, W, op);
+    case 2: return launch_r<T, 2>(c, g, W, op);
+    case 3: return launch_r<T, 3>(c, g, W, op);
+    case 4: return launch_r<T, 4>(c, g, W, op);
+    case 5: return launch_r<T, 5>(c, g, W, op);
+    case 6: return launch_r<T, 6>(c, g, W, op);
+    case 7: return launch_r<T, 7>(c, g, W, op);
+    case 8: return launch_r<T, 8>(c, g, W, op);
+  }
+  set_err(c, "fd_half_width %d out of range", g.R);
+  throw Fail{ALOFDFT_INVALID_ARGUMENT};
+}
+
+void finalize(alofdft_ctx* c, const double* parts, int nparts, int nred, double scale, double* out) {
+  hipLaunchKernelGGL((k_finalize<256>), dim3(1), dim3(256), 0, c->stream, parts, nparts, nred, scale, out);
+  CHECK_LAUNCH(c);
+}
+
+template <typename T>
+void fill(alofdft_ctx* c, T* a, long long n, T v) {
+  const int nb = (int)std::min<long long>(2048, (n + 255) / 256);
+  hipLaunchKernelGGL((k_fill<T>), dim3(std::max(nb, 1)), dim3(256), 0, c->stream, a, n, v);
+  CHECK_LAUNCH(c);
+}
+// A padded work array whose halo and padding are zero for geometry g: zeroed
+// whenever it is first used with a geometry other than the last one.
+template <typename T>
+T* gridbuf(alofdft_ctx* c, const std::string& name, const Geom& g) {
+  T* p = bufT<T>(c, name, g.total);
+  const std::string key = std::to_string(g.nx) + "," + std::to_string(g.ny) + "," + std::to_string(g.nz) + "," +
+                          std::to_string(g.R) + "," + std::to_string((unsigned long long)(uintptr_t)p);
+  auto it = c->geom_key.find(name);
+  if (it == c->geom_key.end() || it->second != key) {
+    fill<T>(c, p, g.total, T(0));
+    c->geom_key[name] = key;
+  }
+  return p;
+}
+
+template <typename TS, typename TD>
+void pack(alofdft_ctx* c, const Geom& g, const TS* dense, TD* padded, int absval = 0) {
+  hipLaunchKernelGGL((k_pack<TS, TD>), dim3(2048), dim3(256), 0, c->stream, g, dense, padded, absval);
+  CHECK_LAUNCH(c);
+}
+template <typename TS, typename TD>
+void unpack(alofdft_ctx* c, const Geom& g, const TS* padded, TD* dense, int absval = 0) {
+  hipLaunchKernelGGL((k_unpack<TS, TD>), dim3(2048), dim3(256), 0, c->stream, g, padded, dense, absval);
+  CHECK_LAUNCH(c);
+}
+
+// ----------------------------------------------------------------- pointwise helpers of the refined solve
+struct ToFloatOp {  // r32 = (float) r64; p32 = r32; x32 = 0; reduce r32.r32 twice (rr, "rhs2")
+  static constexpr int NRED = 2;
+  const double* r64;
+  float* r32;
+  float* p32;
+  float* x32;
+  double* parts_out;
+  template <int NT>
+  __device__ bool begin() { return true; }
+  __device__ void apply(long long i, int, int, int, double* red) const {
+    const float r = (float)r64[i];
+    r32[i] = r;
+    p32[i] = r;
+    x32[i] = 0.0f;
+    const double rd = r;
+    red[0] += rd * rd;
+    red[1] += rd * rd;
+  }
+};
+struct AddFloatOp {  // x64 += (double) x32
+  static constexpr int NRED = 0;
+  double* x64;
+  const float* x32;
+  double* parts_out;
+  template <int NT>
+  __device__ bool begin() { return true; }
+  __device__ void apply(long long i, int, int, int, double*) const { x64[i] += (double)x32[i]; }
+};
+
+// ----------------------------------------------------------------- Poisson CG
+struct CGResult {
+  long long iters = 0;
+  double relres = 0.0;
+  int done = 0;
+};
+
+// CG on A x = rhs (A = -(1/4 pi) Delta_h, zero ghosts) from the guess in x, to
+// r.r <= tol^2 ||rhs||^2 (init = true: the residual is formed here; otherwise r,
+// p0 and the init partials are already prepared by the caller).
+template <typename T>
+CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* rhs, T* x, double tol, long long max_it,
+                  int check_every, const char* tag, bool init = true, const double* init_parts = nullptr,
+                  int init_nparts = 0) {
+  const std::string t(tag);
+  T* r = gridbuf<T>(c, t + ".r", g);
+  T* p0 = gridbuf<T>(c, t + ".p0", g);
+  T* p1 = gridbuf<T>(c, t + ".p1", g);
+  T* Ap = gridbuf<T>(c, t + ".Ap", g);
+  const int maxsb = max_stencil_blocks(g, c->target_blocks);
+  double* partsI = bufT<double>(c, t + ".partsI", (size_t)std::max(maxsb, kPointwiseBlocks) * 2);
+  double* partsA = bufT<double>(c, t + ".partsA", (size_t)maxsb);
+  double* partsB = bufT<double>(c, t + ".partsB", (size_t)kPointwiseBlocks);
+  CGState* st = bufT<CGState>(c, t + ".state", 1);
+  HIPC(c, hipMemsetAsync(st, 0, sizeof(CGState), c->stream));
+  const double* prev = partsI;
+  int nprev = 0;
+  if (init) {
+    CGInitOp<T> op{x, rhs, r, p0, partsI};
+    nprev = launch_stencil(c, g, A, op);
+  } else {
+    prev = init_parts;
+    nprev = init_nparts;
+  }
+  int nred_prev = 2;
+  CGResult res;
+  const double tol2 = tol * tol;
+  long long k = 0;
+  for (;; ++k) {
+    if (k >= max_it) break;
+    T* pold = (k & 1) ? p1 : p0;
+    T* pnew = (k & 1) ? p0 : p1;
+    CGP1Op<T> op1{r, pold, pnew, Ap, st, prev, nprev, nred_prev, (int)k, tol2, partsA, T(0)};
+    const int nb1 = launch_stencil(c, g, A, op1);
+    CGP2Op<T> op2{x, r, pnew, Ap, st, partsA, nb1, (int)k, partsB, T(0)};
+    nprev = launch_pw(c, g, op2);
+    prev = partsB;
+    nred_prev = 1;
+    if ((k + 1) % check_every == 0) {
+      HIPC(c, hipMemcpyAsync(c->pin, st, sizeof(CGState), hipMemcpyDeviceToHost, c->stream));
+      sync(c);
+      if (((CGState*)c->pin)->done) break;
+    }
+  }
+  // one more half iteration to test the last residual if the loop ended without a verdict
+  HIPC(c, hipMemcpyAsync(c->pin, st, sizeof(CGState), hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  CGState s = *(CGState*)c->pin;
+  if (!s.done && k < max_it + 1) {
+    T* pold = (k & 1) ? p1 : p0;
+    T* pnew = (k & 1) ? p0 : p1;
+    CGP1Op<T> op1{r, pold, pnew, Ap, st, prev, nprev, nred_prev, (int)k, tol2, partsA, T(0)};
+    launch_stencil(c, g, A, op1);
+    HIPC(c, hipMemcpyAsync(c->pin, st, sizeof(CGState), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    s = *(CGState*)c->pin;
+  }
+  res.done = s.done;
+  if (s.done == 3) {  // zero right-hand side: the solution is zero
+    fill<T>(c, x, g.total, T(0));
+    res.iters = 0;
+    res.relres = 0.0;
+    return res;
+  }
+  res.iters = s.done ? s.iter : max_it;
+  const double rr = s.done ? s.rr_last : s.rrh[(s.iter) & 1];
+  res.relres = s.rhs2 > 0 ? std::sqrt(rr / s.rhs2) : 0.0;
+  return res;
+}
+
+struct PoissonStats {
+  long long iters = 0, mv64 = 0, mv32 = 0, refinements = 0;
+  double relres = 0.0;
+  int status = 0;
+};
+
+// FP64 solve, or FP32 inner CG (FP64 dots) inside an FP64 iterative-refinement loop.
+PoissonStats poisson(alofdft_ctx* c, const Geom& g, int fdn, double h, int precision, const double* rhs, double* x,
+                     double tol, long long max_cg, int check_every) {
+  PoissonStats ps;
+  const StencilW<double> A64 = stencil_weights<double>(fdn, h, -0.25 / M_PI);
+  if (precision == ALOFDFT_FP64) {
+    CGResult r = cg_solve<double>(c, g, A64, rhs, x, tol, max_cg, check_every, "cg64");
+    ps.iters = r.iters;
+    ps.mv64 = r.iters + 1;
+    ps.relres = r.relres;
+    ps.status = r.done == 2 ? ALOFDFT_NUMERICAL : (r.done ? 0 : ALOFDFT_NOT_CONVERGED);
+    return ps;
+  }
+  const StencilW<float> A32 = stencil_weights<float>(fdn, h, -0.25 / M_PI);
+  double* r64 = gridbuf<double>(c, "ref.r64", g);
+  float* r32 = gridbuf<float>(c, "cg32.r", g);
+  float* p32 = gridbuf<float>(c, "cg32.p0", g);
+  float* x32 = gridbuf<float>(c, "ref.x32", g);
+  const int maxsb = max_stencil_blocks(g, c->target_blocks);
+  double* partsR = bufT<double>(c, "ref.parts", (size_t)std::max(maxsb, kPointwiseBlocks) * 2);
+  double* partsF = bufT<double>(c, "ref.partsF", (size_t)kPointwiseBlocks * 2);
+  double* sc = bufT<double>(c, "ref.sc", 4);
+  const double inner_tol = std::pow(10.0, -c->inner_tol_exp);
+  double rhs2 = -1.0;
+  for (int ref = 0; ref < 60; ++ref) {
+    // FP64 residual r64 = rhs - A x, with r.r and rhs.rhs
+    CGInitOp<double> op{x, rhs, r64, nullptr, partsR};
+    const int nb = launch_stencil(c, g, A64, op);
+    ps.mv64++;
+    finalize(c, partsR, nb, 2, 1.0, sc);
+    HIPC(c, hipMemcpyAsync(c->pin, sc, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    const double rr = c->pin[0];
+    rhs2 = c->pin[1];
+    if (!std::isfinite(rr)) { ps.status = ALOFDFT_NUMERICAL; return ps; }
+    if (rhs2 == 0.0) {
+      fill<double>(c, x, g.total, 0.0);
+      ps.relres = 0.0;
+      return ps;
+    }
+    ps.relres = std::sqrt(rr / rhs2);
+    if (ps.relres <= tol) return ps;
+    if (ps.iters >= max_cg) { ps.status = ALOFDFT_NOT_CONVERGED; return ps; }
+    ps.refinements++;
+    // inner FP32 CG on A e = r64 from e = 0
+    ToFloatOp tf{r64, r32, p32, x32, partsF};
+    const int nbf = launch_pw(c, g, tf);
+    // aim below the outer tolerance without asking FP32 for more than it can give
+    const double want = std::max(inner_tol, 0.5 * tol / ps.relres);
+    CGResult ir = cg_solve<float>(c, g, A32, nullptr, x32, want, max_cg - ps.iters, check_every, "cg32", false,
+                                  partsF, nbf);
+    ps.iters += ir.iters;
+    ps.mv32 += ir.iters;
+    if (ir.done == 2) { ps.status = ALOFDFT_NUMERICAL; return ps; }
+    AddFloatOp add{x, x32, nullptr};
+    launch_pw(c, g, add);
+  }
+  ps.status = ALOFDFT_NOT_CONVERGED;
+  return ps;
+}
+
+// ----------------------------------------------------------------- nuclei on the device
+struct DevAtoms {
+  AtomsDev a;
+};
+
+DevAtoms upload_atoms(alofdft_ctx* c, const alofdft_system* sys, double rc) {
+  const int M = sys->M;
+  // cell list with cells of side >= rc over the box
+  double lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = sys->origin[a] - rc;
+    hi[a] = sys->origin[a] + (sys->n[a] - 1) * sys->h + rc;
+  }
+  const double cs = std::max(rc, 1e-6);
+  int cd[3];
+  for (int a = 0; a < 3; ++a) cd[a] = std::max(1, (int)std::ceil((hi[a] - lo[a]) / cs));
+  const int ncell = cd[0] * cd[1] * cd[2];
+  std::vector<int> cell_of(M), start(ncell + 1, 0), order(M);
+  for (int J = 0; J < M; ++J) {
+    int ci[3];
+    for (int a = 0; a < 3; ++a)
+      ci[a] = std::min(cd[a] - 1, std::max(0, (int)std::floor((sys->R[3 * J + a] - lo[a]) / cs)));
+    cell_of[J] = (ci[2] * cd[1] + ci[1]) * cd[0] + ci[0];
+    start[cell_of[J] + 1]++;
+  }
+  for (int i = 0; i < ncell; ++i) start[i + 1] += start[i];
+  std::vector<int> fillp(start.begin(), start.end() - 1);
+  for (int J = 0; J < M; ++J) order[fillp[cell_of[J]]++] = J;
+  double* dR = bufT<double>(c, "atoms.R", 3 * (size_t)M);
+  double* dZ = bufT<double>(c, "atoms.Z", (size_t)M);
+  int* dS = bufT<int>(c, "atoms.start", (size_t)ncell + 1);
+  int* dA = bufT<int>(c, "atoms.order", (size_t)M);
+  HIPC(c, hipMemcpyAsync(dR, sys->R, 3 * sizeof(double) * M, hipMemcpyHostToDevice, c->stream));
+  HIPC(c, hipMemcpyAsync(dZ, sys->Z, sizeof(double) * M, hipMemcpyHostToDevice, c->stream));
+  HIPC(c, hipMemcpyAsync(dS, start.data(), sizeof(int) * (ncell + 1), hipMemcpyHostToDevice, c->stream));
+  HIPC(c, hipMemcpyAsync(dA, order.data(), sizeof(int) * M, hipMemcpyHostToDevice, c->stream));
+  sync(c);  // host vectors go out of scope
+  DevAtoms d;
+  d.a.R = dR;
+  d.a.Z = dZ;
+  d.a.cell_start = dS;
+  d.a.cell_atoms = dA;
+  d.a.M = M;
+  for (int a = 0; a < 3; ++a) {
+    d.a.cdim[a] = cd[a];
+    d.a.clo[a] = lo[a];
+  }
+  d.a.csize = cs;
+  return d;
+}
+
+void pseudocharge_dev(alofdft_ctx* c, const Geom& g, const alofdft_system* sys, const DevAtoms& at, double s,
+                      double rc, double* b) {
+  fill<double>(c, b, g.total, 0.0);
+  hipLaunchKernelGGL(k_pseudocharge, dim3(4096), dim3(256), 0, c->stream, g, sys->h, sys->origin[0], sys->origin[1],
+                     sys->origin[2], at.a, s, rc, b);
+  CHECK_LAUNCH(c);
+}
+
+// per-atom sums: self energy (phi == nullptr) or force sums (phi != nullptr)
+void atom_sums(alofdft_ctx* c, const Geom& g, const alofdft_system* sys, const DevAtoms& at, double s, double rc,
+               int fdn, const double* phi, std::vector<double>* self, std::vector<double>* force) {
+  const int M = sys->M;
+  double* out = bufT<double>(c, "atoms.out", 4 * (size_t)M);
+  StencilW<double> wt;
+  double w[kMaxRadius + 1];
+  grad_weights(fdn, sys->h, w);
+  wt.c0 = 0.0;
+  for (int p = 0; p <= kMaxRadius; ++p) wt.w[p] = p <= fdn ? w[p] : 0.0;
+  hipLaunchKernelGGL((k_atom_sums<256>), dim3(M), dim3(256), 0, c->stream, g, sys->h, sys->origin[0],
+                     sys->origin[1], sys->origin[2], at.a, s, rc, wt, fdn, phi, self ? out : nullptr,
+                     force ? out + M : nullptr);
+  CHECK_LAUNCH(c);
+  std::vector<double> host(4 * (size_t)M);
+  HIPC(c, hipMemcpyAsync(host.data(), out, sizeof(double) * 4 * M, hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  if (self) self->assign(host.begin(), host.begin() + M);
+  if (force) force->assign(host.begin() + M, host.begin() + 4 * M);
+}
+
+// Appendix-A correction for Gaussian pseudocharges: E_c = 1/2 sum_{I!=J} Z_I Z_J
+// erfc(R_IJ/(sqrt2 s))/R_IJ and f^c = -dE_c/dR.  Pairs beyond 7 sqrt2 s
+// (erfc < 5e-23) are skipped through a cell list.
+double overlap_correction(const alofdft_system* sys, double s, std::vector<double>* fc) {
+  const int M = sys->M;
+  const double a = std::sqrt(2.0) * s, rcut = 7.0 * a;
+  if (fc) fc->assign(3 * (size_t)M, 0.0);
+  double lo[3], hi[3];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = 1e300;
+    hi[d] = -1e300;
+    for (int J = 0; J < M; ++J) {
+      lo[d] = std::min(lo[d], sys->R[3 * J + d]);
+      hi[d] = std::max(hi[d], sys->R[3 * J + d]);
+    }
+  }
+  int cd[3];
+  for (int d = 0; d < 3; ++d) cd[d] = std::max(1, (int)std::ceil((hi[d] - lo[d]) / rcut + 1e-9));
+  std::vector<std::vector<int>> cells((size_t)cd[0] * cd[1] * cd[2]);
+  std::vector<int> ci(3 * (size_t)M);
+  for (int J = 0; J < M; ++J) {
+    for (int d = 0; d < 3; ++d)
+      ci[3 * J + d] = std::min(cd[d] - 1, (int)std::floor((sys->R[3 * J + d] - lo[d]) / rcut));
+    cells[((size_t)ci[3 * J + 2] * cd[1] + ci[3 * J + 1]) * cd[0] + ci[3 * J]].push_back(J);
+  }
+  double E = 0.0;
+  for (int J = 0; J < M; ++J) {
+    for (int z = std::max(0, ci[3 * J + 2] - 1); z <= std::min(cd[2] - 1, ci[3 * J + 2] + 1); ++z)
+      for (int y = std::max(0, ci[3 * J + 1] - 1); y <= std::min(cd[1] - 1, ci[3 * J + 1] + 1); ++y)
+        for (int x = std::max(0, ci[3 * J] - 1); x <= std::min(cd[0] - 1, ci[3 * J] + 1); ++x)
+          for (int I : cells[((size_t)z * cd[1] + y) * cd[0] + x]) {
+            if (I == J) continue;
+            double dv[3];
+            for (int d = 0; d < 3; ++d) dv[d] = sys->R[3 * J + d] - sys->R[3 * I + d];
+            const double r = std::sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+            if (r > rcut) continue;
+            const double ZZ = sys->Z[I] * sys->Z[J];
+            E += 0.5 * ZZ * std::erfc(r / a) / r;
+            if (fc) {
+              const double dF = -std::erfc(r / a) / (r * r) - 2.0 / (a * std::sqrt(M_PI)) * std::exp(-r * r / (a * a)) / r;
+              for (int d = 0; d < 3; ++d) (*fc)[3 * J + d] -= ZZ * dF * dv[d] / r;
+            }
+          }
+  }
+  return E;
+}
+
+// ----------------------------------------------------------------- validation
+void validate(alofdft_ctx* c, const alofdft_system* s, const alofdft_params* p) {
+  require(c, s && p, "null system or params");
+  require(c, p->fd_half_width >= 1 && p->fd_half_width <= kMaxRadius, "fd_half_width must be in 1..8");
+  require(c, std::isfinite(s->h) && s->h > 0, "h must be > 0");
+  for (int a = 0; a < 3; ++a) require(c, s->n[a] >= 2 * p->fd_half_width + 1, "grid smaller than 2n+1 nodes");
+  require(c, s->M >= 1 && s->R && s->Z, "need at least one atom");
+  require(c, std::isfinite(s->N_elec) && s->N_elec > 0, "N must be > 0");
+  require(c, p->lambda > 0 && p->gauss_width > 0 && p->r_cut > 0, "lambda, gauss_width, r_cut must be > 0");
+  require(c, p->method == ALOFDFT_METHOD_AUGMENTED_LAGRANGIAN || p->method == ALOFDFT_METHOD_PENALTY,
+          "method must be augmented Lagrangian or penalty");
+  require(c, p->mu0 > 0 && p->kappa > 0 && p->kappa < 1, "need mu0 > 0 and 0 < kappa < 1");
+  require(c, p->phi_bc == ALOFDFT_BC_ZERO || p->phi_bc == ALOFDFT_BC_MULTIPOLE, "bad phi_bc");
+  require(c, p->precision == ALOFDFT_FP64 || p->precision == ALOFDFT_FP32_REFINED, "bad precision");
+  require(c, p->tol_poisson > 0 && p->tol_grad > 0 && p->tol_constraint > 0, "tolerances must be > 0");
+  require(c, p->cg_check_every >= 1 && p->max_cg >= 1 && p->max_inner >= 1 && p->max_outer >= 1 && p->max_secant >= 1,
+          "iteration caps must be >= 1");
+  for (int J = 0; J < s->M; ++J) {
+    require(c, std::isfinite(s->Z[J]), "non-finite Z");
+    for (int a = 0; a < 3; ++a) {
+      const double x = s->R[3 * J + a];
+      require(c, std::isfinite(x), "non-finite atom position");
+      const double lo = s->origin[a], hi = s->origin[a] + (s->n[a] - 1) * s->h;
+      require(c, x - p->r_cut >= lo - 1e-9 && x + p->r_cut <= hi + 1e-9, "an atom's r_cut ball leaves the box");
+    }
+  }
+}
+
+// ----------------------------------------------------------------- the solver
+uint64_t splitmix64(uint64_t state) {
+  uint64_t z = state + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+struct Eval {  // host copy of one evaluation's scalars
+  double upd[kUpdRed];  // h^3-scaled
+  double gr[G_NRED];    // raw sums
+};
+
+class Solver {
+ public:
+  Solver(alofdft_ctx* c, const alofdft_system* sys, const alofdft_params* prm)
+      : c_(c), S_(sys), P_(prm) {
+    g_ = make_geom(sys->n, prm->fd_half_width);
+    h3_ = sys->h * sys->h * sys->h;
+    const size_t T = g_.total;
+    us_ = bufT<double>(c, "s.us", T);
+    v_ = bufT<double>(c, "s.v", T);
+    d_ = bufT<double>(c, "s.d", T);
+    sa_ = bufT<double>(c, "s.sa", T);
+    sb_ = bufT<double>(c, "s.sb", T);
+    b_ = bufT<double>(c, "s.b", T);
+    phi_ = bufT<double>(c, "s.phi", T);
+    rhs_ = bufT<double>(c, "s.rhs", T);
+    partsU_ = bufT<double>(c, "s.partsU", (size_t)kPointwiseBlocks * kUpdRed);
+    partsG_ = bufT<double>(c, "s.partsG", (size_t)max_stencil_blocks(g_, c->target_blocks) * G_NRED);
+    scal_ = bufT<double>(c, "s.scal", kUpdRed + G_NRED + 8);
+    double w[kMaxRadius + 1];
+    lap_weights(prm->fd_half_width, sys->h, w);
+    vw_diag_ = -3.0 * prm->lambda * w[0];
+    Wlap_ = stencil_weights<double>(prm->fd_half_width, sys->h, 1.0);
+    frame_.h = sys->h;
+    frame_.hx = 0.5 * (sys->n[0] - 1);
+    frame_.hy = 0.5 * (sys->n[1] - 1);
+    frame_.hz = 0.5 * (sys->n[2] - 1);
+    CF_ = 0.3 * std::pow(3.0 * M_PI * M_PI, 2.0 / 3.0);
+  }
+
+  // Zero all work arrays (halo included) and set up the nuclei.
+  void setup(const double* u0_dense_dev, bool u0_abs) {
+    for (double* a : {us_, v_, d_, sa_, sb_, b_, phi_, rhs_}) fill<double>(c_, a, g_.total, 0.0);
+    at_ = upload_atoms(c_, S_, P_->r_cut);
+    pseudocharge_dev(c_, g_, S_, at_, P_->gauss_width, P_->r_cut, b_);
+    std::vector<double> self;
+    atom_sums(c_, g_, S_, at_, P_->gauss_width, P_->r_cut, P_->fd_half_width, nullptr, &self, nullptr);
+    E_self_ = 0.0;
+    for (double x : self) E_self_ += 0.5 * h3_ * x;
+    E_c_ = overlap_correction(S_, P_->gauss_width, nullptr);
+    pack<double, double>(c_, g_, u0_dense_dev, us_, u0_abs ? 1 : 0);
+  }
+
+  // Evaluate at v = u_start + t d (trial) or with the direction update fused (dir).
+  void eval_trial(double t, double eta, double mu, bool with_dir, double beta, Eval& ev) {
+    if (with_dir) {
+      DirOp op{us_, d_, s_new(), v_, b_, beta, t, frame_, partsU_};
+      nU_ = launch_pw(c_, g_, op);
+      std::swap(s_cur_, s_prev_);  // the s just used becomes s_old of the next gradient
+    } else {
+      TrialOp op{us_, d_, b_, v_, t, frame_, partsU_};
+      nU_ = launch_pw(c_, g_, op);
+    }
+    eval_at_v(eta, mu, ev);
+  }
+
+  void eval_at_v(double eta, double mu, Eval& ev) {
+    double* upd = scal_;
+    double* gsc = scal_ + kUpdRed;
+    finalize(c_, partsU_, nU_, kUpdRed, h3_, upd);
+    RhsOp<double> rop{v_, b_, rhs_, P_->phi_bc == ALOFDFT_BC_MULTIPOLE ? upd : nullptr, Wlap_, g_.R,
+                      g_.nx, g_.ny, g_.nz, frame_, nullptr};
+    // RhsOp reads unscaled weights w[p]
+    double w[kMaxRadius + 1];
+    lap_weights(P_->fd_half_width, S_->h, w);
+    for (int p = 0; p <= kMaxRadius; ++p) rop.W.w[p] = p <= P_->fd_half_width ? w[p] : 0.0;
+    launch_pw(c_, g_, rop);
+    auto t0 = std::chrono::steady_clock::now();
+    PoissonStats ps = poisson(c_, g_, P_->fd_half_width, S_->h, P_->precision, rhs_, phi_, P_->tol_poisson,
+                              P_->max_cg, P_->cg_check_every);
+    auto t1 = std::chrono::steady_clock::now();
+    time_poisson_ += std::chrono::duration<double, std::milli>(t1 - t0).count();
+    counts_.poisson_solves++;
+    counts_.cg_iters += ps.iters;
+    counts_.matvec_fp64 += ps.mv64;
+    counts_.matvec_fp32 += ps.mv32;
+    counts_.refinements += ps.refinements;
+    relres_ = ps.relres;
+    if (ps.status == ALOFDFT_NUMERICAL) {
+      set_err(c_, "non-finite value in the Poisson solve");
+      throw Fail{ALOFDFT_NUMERICAL};
+    }
+    if (ps.status == ALOFDFT_NOT_CONVERGED) poisson_capped_ = true;
+    GradOp gop{v_, phi_, b_, d_, s_old(), s_new(), gout_, upd, 0.5 * P_->lambda, eta, mu > 0 ? 1.0 / mu : 0.0,
+               vw_diag_, CF_, P_->xc, partsG_, 0.0};
+    gop.Cptr = upd;
+    // shift uses C = h^3 sum v^2 - N: pass N through eta (eta' = eta + N/mu)
+    gop.eta = eta + (mu > 0 ? S_->N_elec / mu : 0.0);
+    const int nG = launch_stencil(c_, g_, Wlap_, gop);
+    finalize(c_, partsG_, nG, G_NRED, 1.0, gsc);
+    HIPC(c_, hipMemcpyAsync(c_->pin, scal_, sizeof(double) * (kUpdRed + G_NRED), hipMemcpyDeviceToHost, c_->stream));
+    sync(c_);
+    std::memcpy(ev.upd, c_->pin, sizeof(double) * kUpdRed);
+    std::memcpy(ev.gr, c_->pin + kUpdRed, sizeof(double) * G_NRED);
+    time_grad_ += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
+    counts_.grad_evals++;
+    counts_.matvec_fp64++;
+    for (int i = 0; i < G_NRED; ++i)
+      if (!std::isfinite(ev.gr[i])) {
+        set_err(c_, "non-finite value in the residual evaluation");
+        throw Fail{ALOFDFT_NUMERICAL};
+      }
+  }
+
+  double C_of(const Eval& e) const { return e.upd[0] - S_->N_elec; }
+  double energy(const Eval& e, alofdft_energy* out = nullptr) const {
+    const double ETF = CF_ * h3_ * e.gr[G_TF];
+    const double EvW = -0.5 * P_->lambda * h3_ * e.gr[G_VW];
+    const double Exc = h3_ * e.gr[G_XC];
+    const double Ees = 0.5 * h3_ * e.gr[G_ES] - E_self_;
+    const double E = ETF + EvW + Exc + Ees + E_c_;
+    if (out) {
+      out->E_TF = ETF;
+      out->E_vW = EvW;
+      out->E_xc = Exc;
+      out->E_es = Ees;
+      out->E_self = E_self_;
+      out->E_corr = E_c_;
+      out->E_total = E;
+      out->C_h = C_of(e);
+      out->grad_norm = std::sqrt(h3_ * e.gr[G_GG]);
+    }
+    return E;
+  }
+
+  // Nonlinear CG on L(.; eta, mu) (see the line-search reading in DESIGN notes of
+  // the oracle: secant on the derivative along |u + t d|, bracketed).  On entry
+  // `cur` holds the evaluation at v (which is the current point).
+  int nlcg(double eta, double mu, Eval& cur, double& gnorm, long long& its) {
+    double gn = std::sqrt(h3_ * cur.gr[G_GG]);
+    // s_cur_ holds -g/M of the current point; first direction d = s
+    double delta_new = -cur.gr[G_GS_NEW];
+    double beta = 0.0;
+    bool restart = true;
+    int since_restart = 0;
+    int status = 1;
+    its = 0;
+    double gd_unsigned = cur.gr[G_GD];
+    for (;;) {
+      if (!std::isfinite(gn)) { status = ALOFDFT_NUMERICAL; break; }
+      if (gn < P_->tol_grad) { status = 0; break; }
+      if (its >= P_->max_inner) { status = 1; break; }
+      // direction d = s + beta d (beta = 0 on restart); derivative at t = 0
+      double slope0 = -delta_new + (restart ? 0.0 : beta * gd_unsigned);
+      if (!restart && !(slope0 < 0.0)) {
+        restart = true;
+        since_restart = 0;
+        slope0 = -delta_new;
+      }
+      const double bet = restart ? 0.0 : beta;
+      if (restart) {
+        // d = s: DirOp with beta 0 overwrites d
+      }
+      // first probe fused with the direction update and the projection u = |v|
+      Eval ev;
+      double t_cur = P_->sigma0;
+      eval_trial(t_cur, eta, mu, true, bet, ev);
+      double s_cur = ev.gr[G_SLOPE];
+      double a = 0.0, b = INFINITY, t_prev = 0.0, s_prev = slope0;
+      if (s_cur > 0.0) b = t_cur; else a = t_cur;
+      for (int j = 0; j < P_->max_secant; ++j) {
+        if (std::fabs(s_cur) <= P_->secant_rel * std::fabs(slope0)) break;
+        const double curv = (s_cur - s_prev) / (t_cur - t_prev);
+        double t_new = curv > 0.0 ? t_cur - s_cur / curv : NAN;
+        const double hi = std::isfinite(b) ? b : 4.0 * std::max(a, t_cur);
+        if (!(t_new > a && t_new < hi)) t_new = std::isfinite(b) ? 0.5 * (a + b) : 2.0 * std::max(a, t_cur);
+        t_prev = t_cur;
+        s_prev = s_cur;
+        t_cur = t_new;
+        eval_trial(t_cur, eta, mu, false, 0.0, ev);
+        s_cur = ev.gr[G_SLOPE];
+        if (s_cur > 0.0) b = std::min(b, t_cur); else a = std::max(a, t_cur);
+      }
+      cur = ev;
+      gn = std::sqrt(h3_ * cur.gr[G_GG]);
+      const double delta_old = delta_new;
+      const double delta_mid = -cur.gr[G_GS_OLD];
+      delta_new = -cur.gr[G_GS_NEW];
+      beta = (delta_new - delta_mid) / delta_old;
+      gd_unsigned = cur.gr[G_GD];
+      ++since_restart;
+      restart = since_restart >= P_->restart_every || beta <= 0.0;
+      if (restart) since_restart = 0;
+      ++its;
+    }
+    gnorm = gn;
+    return status;
+  }
+
+  int run(alofdft_result* res) {
+    auto t0 = std::chrono::steady_clock::now();
+    counts_ = alofdft_counts{};
+    // v = u0 (t = 0 trial from u_start = u0, d = 0)
+    Eval cur;
+    double eta = P_->method == ALOFDFT_METHOD_PENALTY ? 0.0 : P_->eta0;
+    double mu = P_->mu0;
+    eval_trial(0.0, eta, mu, false, 0.0, cur);
+    time_setup_ = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    int status = ALOFDFT_NOT_CONVERGED;
+    double E_prev = 0.0, gn = 0.0, dE = 0.0, eta_star = eta;
+    for (int q = 0; q < P_->max_outer; ++q) {
+      if (q > 0) eval_at_v_refresh(eta, mu, cur);  // same u, new eta/mu: recompute residual terms
+      long long its = 0;
+      const int st = nlcg(eta, mu, cur, gn, its);
+      counts_.inner += its;
+      counts_.outer = q + 1;
+      if (st == ALOFDFT_NUMERICAL) {
+        status = ALOFDFT_NUMERICAL;
+        break;
+      }
+      const double C = C_of(cur);
+      const double E = energy(cur);
+      dE = q == 0 ? 0.0 : E - E_prev;
+      E_prev = E;
+      eta_star = eta - C / mu;  // Algorithm AugLag multiplier update
+      if (std::fabs(C) / S_->N_elec < P_->tol_constraint && st == 0) {
+        status = ALOFDFT_OK;
+        break;
+      }
+      eta = P_->method == ALOFDFT_METHOD_PENALTY ? 0.0 : eta_star;
+      mu *= P_->kappa;
+    }
+    if (status == ALOFDFT_OK && poisson_capped_) status = ALOFDFT_NOT_CONVERGED;
+    alofdft_energy en;
+    energy(cur, &en);
+    res->E_total = en.E_total;
+    res->E_TF = en.E_TF;
+    res->E_vW = en.E_vW;
+    res->E_xc = en.E_xc;
+    res->E_es = en.E_es;
+    res->E_self = en.E_self;
+    res->E_corr = en.E_corr;
+    res->eta_star = eta_star;
+    res->C_h = en.C_h;
+    res->grad_norm = en.grad_norm;
+    res->poisson_relres = relres_;
+    res->dE_last = dE;
+    res->counts = counts_;
+    res->time_poisson_ms = time_poisson_;
+    res->time_grad_ms = time_grad_;
+    res->time_setup_ms = time_setup_;
+    res->status = status;
+    return status;
+  }
+
+  // Re-evaluate the residual at the same v after eta/mu changed (no Poisson
+  // solve is needed: phi depends on u only, but the slope/preconditioner sums
+  // do).  Implemented as a fresh evaluation at t = 0 of the current point.
+  void eval_at_v_refresh(double eta, double mu, Eval& cur) {
+    TrialOp op{v_, zero_dir(), b_, v_, 0.0, frame_, partsU_};
+    nU_ = launch_pw(c_, g_, op);
+    eval_at_v(eta, mu, cur);
+  }
+
+  double* zero_dir() {
+    double* z = gridbuf<double>(c_, "s.zero", g_);
+    return z;
+  }
+
+  // projection u = |v| into the dense output
+  void output(double* u_dense_dev, double* phi_dense_dev) {
+    if (u_dense_dev) unpack<double, double>(c_, g_, v_, u_dense_dev, 1);
+    if (phi_dense_dev) unpack<double, double>(c_, g_, phi_, phi_dense_dev, 0);
+  }
+
+  void forces(double* out) {
+    std::vector<double> f, fc;
+    atom_sums(c_, g_, S_, at_, P_->gauss_width, P_->r_cut, P_->fd_half_width, phi_, nullptr, &f);
+    overlap_correction(S_, P_->gauss_width, &fc);
+    for (int i = 0; i < 3 * S_->M; ++i) out[i] = h3_ * f[i] + fc[i];
+  }
+
+  const Geom& geom() const { return g_; }
+  double* phi() { return phi_; }
+  double* v() { return v_; }
+  double* b() { return b_; }
+  double E_self() const { return E_self_; }
+  double E_c() const { return E_c_; }
+  void set_gout(double* p) { gout_ = p; }
+  const alofdft_counts& counts() const { return counts_; }
+
+ private:
+  double* s_new() { return s_cur_ ? sb_ : sa_; }
+  double* s_old() { return s_cur_ ? sa_ : sb_; }
+  alofdft_ctx* c_;
+  const alofdft_system* S_;
+  const alofdft_params* P_;
+  Geom g_;
+  double h3_;
+  double *us_, *v_, *d_, *sa_, *sb_, *b_, *phi_, *rhs_, *partsU_, *partsG_, *scal_;
+  double* gout_ = nullptr;
+  int s_cur_ = 0, s_prev_ = 1;
+  int nU_ = 0;
+  double vw_diag_, CF_;
+  StencilW<double> Wlap_;
+  BoxFrame frame_;
+  DevAtoms at_;
+  double E_self_ = 0.0, E_c_ = 0.0;
+  alofdft_counts counts_{};
+  double relres_ = 0.0;
+  bool poisson_capped_ = false;
+  double time_poisson_ = 0.0, time_grad_ = 0.0, time_setup_ = 0.0;
+};
+
+int guarded(alofdft_ctx* c, const std::function<int()>& f);
+
+}  // namespace
+
+// ================================================================= C ABI
+namespace {
+
+int guarded(alofdft_ctx* c, const std::function<int()>& f) {
+  try {
+    if (c) {
+      hipError_t e = hipSetDevice(c->device);
+      if (e != hipSuccess) {
+        set_err(c, "hipSetDevice(%d): %s", c->device, hipGetErrorString(e));
+        return ALOFDFT_DEVICE_ERROR;
+      }
+    }
+    return f();
+  } catch (const Fail& e) {
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_err(c, "host allocation failed");
+    return ALOFDFT_OUT_OF_MEMORY;
+  } catch (...) {
+    set_err(c, "unexpected exception");
+    return ALOFDFT_DEVICE_ERROR;
+  }
+}
+
+// Default initial guess u0 = sqrt(N/V)(1 + 0.05 xi), xi = 2 U(SplitMix64(seed ^ i)) - 1.
+std::vector<double> default_u0(const alofdft_system* s, uint64_t seed) {
+  const long long n = (long long)s->n[0] * s->n[1] * s->n[2];
+  const double V = (double)n * s->h * s->h * s->h;
+  const double a = std::sqrt(s->N_elec / V);
+  std::vector<double> u(n);
+  for (long long i = 0; i < n; ++i) {
+    const uint64_t z = splitmix64(seed ^ (uint64_t)i);
+    const double xi = 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
+    u[i] = a * (1.0 + 0.05 * xi);
+  }
+  return u;
+}
+
+long long npoints(const int n[3]) { return (long long)n[0] * n[1] * n[2]; }
+
+int solve_impl(alofdft_ctx* c, const alofdft_system* sys, const alofdft_params* prm, const double* u0_dev,
+               const double* u0_host, double* u_out_dev, double* phi_out_dev, double* forces, alofdft_result* res) {
+  require(c, res != nullptr, "result pointer is null");
+  std::memset(res, 0, sizeof(*res));
+  validate(c, sys, prm);
+  auto t0 = std::chrono::steady_clock::now();
+  const long long n = npoints(sys->n);
+  double* u0 = bufT<double>(c, "io.u0", (size_t)n);
+  if (u0_dev) {
+    HIPC(c, hipMemcpyAsync(u0, u0_dev, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+  } else {
+    std::vector<double> h = u0_host ? std::vector<double>(u0_host, u0_host + n) : default_u0(sys, prm->seed);
+    for (double x : h) require(c, std::isfinite(x), "non-finite initial guess");
+    HIPC(c, hipMemcpyAsync(u0, h.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+    sync(c);
+  }
+  Solver S(c, sys, prm);
+  S.setup(u0, true);
+  int st = S.run(res);
+  S.output(u_out_dev, phi_out_dev);
+  if (forces) S.forces(forces);
+  sync(c);
+  res->time_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* alofdft_strerror(int s) {
+  switch (s) {
+    case ALOFDFT_OK: return "ok";
+    case ALOFDFT_NOT_CONVERGED: return "not converged (outputs hold the last iterate)";
+    case ALOFDFT_PENDING: return "pending";
+    case ALOFDFT_INVALID_ARGUMENT: return "invalid argument";
+    case ALOFDFT_OUT_OF_MEMORY: return "out of memory";
+    case ALOFDFT_DEVICE_ERROR: return "device error";
+    case ALOFDFT_NUMERICAL: return "non-finite value";
+    case ALOFDFT_REJECTED: return "rejected";
+  }
+  return "unknown status";
+}
+
+const char* alofdft_last_error(const alofdft_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int alofdft_default_params(alofdft_params* p) {
+  if (!p) return ALOFDFT_INVALID_ARGUMENT;
+  std::memset(p, 0, sizeof(*p));
+  p->fd_half_width = 6;
+  p->lambda = 0.2;
+  p->xc = ALOFDFT_XC_LDA_PZ;
+  p->gauss_width = 1.0;
+  p->r_cut = 7.0;
+  p->method = ALOFDFT_METHOD_AUGMENTED_LAGRANGIAN;
+  p->eta0 = -0.2;
+  p->mu0 = 1.0;
+  p->kappa = 0.1;
+  p->tol_constraint = 1e-8;
+  p->tol_grad = 1e-6;
+  p->tol_poisson = 1e-10;
+  p->phi_bc = ALOFDFT_BC_MULTIPOLE;
+  p->precision = ALOFDFT_FP64;
+  p->max_outer = 30;
+  p->max_inner = 20000;
+  p->max_cg = 100000;
+  p->sigma0 = 0.5;
+  p->max_secant = 4;
+  p->secant_rel = 0.1;
+  p->restart_every = 50;
+  p->cg_check_every = 16;
+  p->seed = 6456;
+  return ALOFDFT_OK;
+}
+
+int alofdft_create(alofdft_ctx** out, int hip_device, void* hip_stream) {
+  if (!out) return ALOFDFT_INVALID_ARGUMENT;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) return ALOFDFT_DEVICE_ERROR;
+  alofdft_ctx* c = new (std::nothrow) alofdft_ctx();
+  if (!c) return ALOFDFT_OUT_OF_MEMORY;
+  c->device = hip_device;
+  c->stream = (hipStream_t)hip_stream;
+  int st = guarded(c, [&]() {
+    HIPC(c, hipHostMalloc((void**)&c->pin, 4096, hipHostMallocDefault));
+    HIPC(c, hipEventCreate(&c->ev0));
+    HIPC(c, hipEventCreate(&c->ev1));
+    return ALOFDFT_OK;
+  });
+  if (st != ALOFDFT_OK) {
+    alofdft_destroy(c);
+    return st;
+  }
+  *out = c;
+  return ALOFDFT_OK;
+}
+
+void alofdft_destroy(alofdft_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
+  for (auto& kv : c->bufs) (void)hipFree(kv.second.first);
+  if (c->pin) (void)hipHostFree(c->pin);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  delete c;
+}
+
+int alofdft_set_tuning(alofdft_ctx* c, int stencil_variant, int target_blocks, int inner_tol_exp) {
+  if (!c || stencil_variant < 0 || stencil_variant > 4 || target_blocks < 1 || inner_tol_exp < 1 || inner_tol_exp > 7)
+    return ALOFDFT_INVALID_ARGUMENT;
+  c->variant = stencil_variant;
+  c->target_blocks = target_blocks;
+  c->inner_tol_exp = inner_tol_exp;
+  return ALOFDFT_OK;
+}
+
+int alofdft_solve(alofdft_ctx* c, const alofdft_system* sys, const alofdft_params* prm, const double* u0,
+                  double* u_out, double* phi_out, double* forces_out, alofdft_result* res) {
+  if (!c) return ALOFDFT_INVALID_ARGUMENT;
+  return guarded(c, [&]() {
+    require(c, sys != nullptr, "null system");
+    const long long n = npoints(sys->n);
+    double* du = u_out ? bufT<double>(c, "io.uout", (size_t)n) : nullptr;
+    double* dp = phi_out ? bufT<double>(c, "io.phiout", (size_t)n) : nullptr;
+    int st = solve_impl(c, sys, prm, nullptr, u0, du, dp, forces_out, res);
+    if (u_out) HIPC(c, hipMemcpyAsync(u_out, du, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    if (phi_out) HIPC(c, hipMemcpyAsync(phi_out, dp, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    return st;
+  });
+}
+
+int alofdft_solve_device(alofdft_ctx* c, const alofdft_system* sys, const alofdft_params* prm, const double* u0_dev,
+                         double* u_out_dev, double* phi_out_dev, double* forces_out, alofdft_result* res) {
+  if (!c) return ALOFDFT_INVALID_ARGUMENT;
+  return guarded(c, [&]() { return solve_impl(c, sys, prm, u0_dev, nullptr, u_out_dev, phi_out_dev, forces_out, res); });
+}
+
+int alofdft_apply_laplacian(alofdft_ctx* c, const int n[3], double h, int fdn, int dtype, const void* x, void* y) {
+  if (!c) return ALOFDFT_INVALID_ARGUMENT;
+  return guarded(c, [&]() {
+    require(c, n && x && y, "null argument");
+    require(c, fdn >= 1 && fdn <= kMaxRadius, "fd_half_width must be in 1..8");
+    require(c, h > 0 && std::isfinite(h), "h must be > 0");
+    require(c, dtype == 0 || dtype == 1, "dtype must be 0 (double) or 1 (float)");
+    for (int a = 0; a < 3; ++a) require(c, n[a] >= 1, "n must be >= 1");
+    const Geom g = make_geom(n, fdn);
+    if (dtype == 0) {
+      double* px = bufT<double>(c, "lap.x", g.total);
+      double* py = bufT<double>(c, "lap.y", g.total);
+      fill<double>(c, px, g.total, 0.0);
+      pack<double, double>(c, g, (const double*)x, px);
+      LapOp<double> op{px, py, nullptr};
+      launch_stencil(c, g, stencil_weights<double>(fdn, h, 1.0), op);
+      unpack<double, double>(c, g, py, (double*)y);
+    } else {
+      float* px = bufT<float>(c, "lapf.x", g.total);
+      float* py = bufT<float>(c, "lapf.y", g.total);
+      fill<float>(c, px, g.total, 0.0f);
+      pack<float, float>(c, g, (const float*)x, px);
+      LapOp<float> op{px, py, nullptr};
+      launch_stencil(c, g, stencil_weights<float>(fdn, h, 1.0), op);
+      unpack<float, float>(c, g, py, (float*)y);
+    }
+    sync(c);
+    return ALOFDFT_OK;
+  });
+}
+
+int alofdft_poisson(alofdft_ctx* c, const int n[3], double h, const double origin[3], int fdn, int bc, int precision,
+                    const double* rho, double* phi, double tol, int max_cg, long long* iters, double* relres) {
+  if (!c) return ALOFDFT_INVALID_ARGUMENT;
+  return guarded(c, [&]() {
+    require(c, n && origin && rho && phi, "null argument");
+    require(c, fdn >= 1 && fdn <= kMaxRadius, "fd_half_width must be in 1..8");
+    require(c, h > 0 && std::isfinite(h) && tol > 0 && max_cg >= 1, "bad h, tol or max_cg");
+    require(c, bc == ALOFDFT_BC_ZERO || bc == ALOFDFT_BC_MULTIPOLE, "bad bc");
+    require(c, precision == ALOFDFT_FP64 || precision == ALOFDFT_FP32_REFINED, "bad precision");
+    for (int a = 0; a < 3; ++a) require(c, n[a] >= 2 * fdn + 1, "grid smaller than 2n+1 nodes");
+    (void)origin;  // the boundary expansion uses offsets from the box centre only
+    const Geom g = make_geom(n, fdn);
+    double* b = bufT<double>(c, "po.rho", g.total);
+    double* zero = bufT<double>(c, "po.zero", g.total);
+    double* v = bufT<double>(c, "po.v", g.total);
+    double* rhs = bufT<double>(c, "po.rhs", g.total);
+    double* x = bufT<double>(c, "po.x", g.total);
+    double* parts = bufT<double>(c, "po.parts", (size_t)kPointwiseBlocks * kUpdRed);
+    double* mom = bufT<double>(c, "po.mom", kUpdRed);
+    for (double* a : {b, zero, v, rhs, x}) fill<double>(c, a, g.total, 0.0);
+    pack<double, double>(c, g, rho, b);
+    pack<double, double>(c, g, phi, x);
+    BoxFrame f{h, 0.5 * (n[0] - 1), 0.5 * (n[1] - 1), 0.5 * (n[2] - 1)};
+    TrialOp top{zero, zero, b, v, 0.0, f, parts};
+    const int nb = launch_pw(c, g, top);
+    finalize(c, parts, nb, kUpdRed, h * h * h, mom);
+    RhsOp<double> rop{v, b, rhs, bc == ALOFDFT_BC_MULTIPOLE ? mom : nullptr, stencil_weights<double>(fdn, h, 1.0),
+                      fdn, n[0], n[1], n[2], f, nullptr};
+    launch_pw(c, g, rop);
+    PoissonStats ps = poisson(c, g, fdn, h, precision, rhs, x, tol, max_cg, 16);
+    unpack<double, double>(c, g, x, phi);
+    sync(c);
+    if (iters) *iters = ps.iters;
+    if (relres) *relres = ps.relres;
+    return ps.status;
+  });
+}
+
+int alofdft_energy_gradient(alofdft_ctx* c, const alofdft_system* sys, const alofdft_params* prm, const double* u,
+                            double eta, double mu, double* phi, double* g, alofdft_energy* e) {
+  if (!c) return ALOFDFT_INVALID_ARGUMENT;
+  return guarded(c, [&]() {
+    require(c, u && phi && e, "null argument");
+    validate(c, sys, prm);
+    Solver S(c, sys, prm);
+    S.setup(u, false);
+    pack<double, double>(c, S.geom(), phi, S.phi());
+    double* gp = nullptr;
+    if (g) {
+      gp = bufT<double>(c, "eg.g", S.geom().total);
+      S.set_gout(gp);
+    }
+    Eval ev;
+    S.eval_trial(0.0, eta, mu, false, 0.0, ev);
+    S.energy(ev, e);
+    e->L = e->E_total - eta * e->C_h + (mu > 0 ? e->C_h * e->C_h / (2.0 * mu) : 0.0);
+    e->cg_iters = S.counts().cg_iters;
+    unpack<double, double>(c, S.geom(), S.phi(), phi);
+    if (g) unpack<double, double>(c, S.geom(), gp, g);
+    sync(c);
+    return ALOFDFT_OK;
+  });
+}
+
+int alofdft_pseudocharge(alofdft_ctx* c, const alofdft_system* sys, const alofdft_params* prm, double* b,
+                         double* self_energy) {
+  if (!c) return ALOFDFT_INVALID_ARGUMENT;
+  return guarded(c, [&]() {
+    require(c, b != nullptr, "null argument");
+    validate(c, sys, prm);
+    Solver S(c, sys, prm);
+    double* z = bufT<double>(c, "pc.zero", (size_t)npoints(sys->n));
+    S.setup(z, false);
+    unpack<double, double>(c, S.geom(), S.b(), b);
+    if (self_energy) *self_energy = S.E_self();
+    sync(c);
+    return ALOFDFT_OK;
+  });
+}
+
+int alofdft_forces(alofdft_ctx* c, const alofdft_system* sys, const alofdft_params* prm, const double* phi,
+                   double* forces) {
+  if (!c) return ALOFDFT_INVALID_ARGUMENT;
+  return guarded(c, [&]() {
+    require(c, phi && forces, "null argument");
+    validate(c, sys, prm);
+    Solver S(c, sys, prm);
+    double* z = bufT<double>(c, "pc.zero", (size_t)npoints(sys->n));
+    S.setup(z, false);
+    pack<double, double>(c, S.geom(), phi, S.phi());
+    S.forces(forces);
+    return ALOFDFT_OK;
+  });
+}
+
+int alofdft_bench_stencil(alofdft_ctx* c, const int n[3], int fdn, int dtype, int reps, int nbuf, double* ms) {
+  if (!c) return ALOFDFT_INVALID_ARGUMENT;
+  return guarded(c, [&]() {
+    require(c, n && ms && reps >= 1 && nbuf >= 1 && nbuf <= 64, "bad argument");
+    require(c, fdn >= 1 && fdn <= kMaxRadius && (dtype == 0 || dtype == 1), "bad order or dtype");
+    const Geom g = make_geom(n, fdn);
+    std::vector<void*> xs(nbuf), ys(nbuf);
+    const size_t es = dtype == 0 ? sizeof(double) : sizeof(float);
+    for (int i = 0; i < nbuf; ++i) {
+      xs[i] = buf(c, "bench.x" + std::to_string(i), g.total * es);
+      ys[i] = buf(c, "bench.y" + std::to_string(i), g.total * es);
+      if (dtype == 0) fill<double>(c, (double*)xs[i], g.total, 1.0 + 0.01 * i);
+      else fill<float>(c, (float*)xs[i], g.total, 1.0f + 0.01f * i);
+    }
+    auto once = [&](int i) {
+      const int b = i % nbuf;
+      if (dtype == 0) {
+        LapOp<double> op{(const double*)xs[b], (double*)ys[b], nullptr};
+        launch_stencil(c, g, stencil_weights<double>(fdn, 0.5, 1.0), op);
+      } else {
+        LapOp<float> op{(const float*)xs[b], (float*)ys[b], nullptr};
+        launch_stencil(c, g, stencil_weights<float>(fdn, 0.5, 1.0), op);
+      }
+    };
+    for (int i = 0; i < std::min(reps, 10); ++i) once(i);
+    HIPC(c, hipEventRecord(c->ev0, c->stream));
+    for (int i = 0; i < reps; ++i) once(i);
+    HIPC(c, hipEventRecord(c->ev1, c->stream));
+    HIPC(c, hipEventSynchronize(c->ev1));
+    float t = 0.f;
+    HIPC(c, hipEventElapsedTime(&t, c->ev0, c->ev1));
+    *ms = (double)t / reps;
+    return ALOFDFT_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,59 @@
+"""GPU ground-state solves against the CPU oracle (energy per atom, forces, u, phi)."""
+import numpy as np
+import pytest
+
+from paper_1405_6456_amd import synth
+from tests.gpu_util import ctx, golden
+
+pytestmark = pytest.mark.gpu
+
+E_TOL_FP64 = 1e-6   # Ha/atom
+F_TOL = 1e-4        # Ha/Bohr
+E_TOL_MIXED = 1e-5  # Ha/atom
+
+
+@pytest.fixture(scope="module")
+def C():
+    c = ctx()
+    yield c
+    c.close()
+
+
+def small_pair():
+    n = 21
+    g = synth.Grid((n, n, n), 0.9, (0.0, 0.0, 0.0))
+    R = np.array([[9.0, 9.0, 7.0], [9.05, 8.9, 11.0]])
+    return synth.System("pair", g, R, np.array([3.0, 3.0]), 6.0)
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_small_pair_matches_oracle_live(C, orc, method):
+    import paper_1405_6456_amd as lib
+
+    S = small_pair()
+    u0 = synth.initial_u(S.grid, S.N)
+    ref = orc.solve(S, orc.params(method=method), u0)
+    out = C.solve(S, lib.default_params(method=method), u0)
+    assert out["status"] == 0
+    assert abs(out["E_total"] - ref["E_total"]) / S.M < E_TOL_FP64
+    assert np.abs(out["forces"] - ref["forces"]).max() < F_TOL
+    assert abs(out["eta_star"] - ref["eta"]) < 1e-6
+    assert np.abs(out["u"] - ref["u"]).max() < 1e-5 * np.abs(ref["u"]).max()
+
+
+@pytest.mark.parametrize("name", ["single", "fcc2"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_workload_matches_oracle_fixture(C, name, precision):
+    import paper_1405_6456_amd as lib
+
+    gold = golden(name)
+    S = synth.config(name)
+    out = C.solve(S, lib.default_params(precision=precision), synth.initial_u(S.grid, S.N))
+    assert out["status"] == 0
+    etol = E_TOL_FP64 if precision == 0 else E_TOL_MIXED
+    assert abs(out["E_total"] - gold["result"]["E_total"]) / S.M < etol
+    assert np.abs(out["forces"] - np.array(gold["forces"])).max() < F_TOL
+    assert abs(out["C_h"]) / S.N < 1e-8
+    u = out["u"]
+    us = np.array([u[k, j, i] for i, j, k in gold["sample_nodes"]])
+    assert np.abs(us - np.array(gold["u_samples"])).max() < 1e-4 * np.abs(u).max()

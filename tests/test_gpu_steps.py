@@ -1,0 +1,188 @@
+"""GPU parity of the individual steps (through the C ABI) against the CPU oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1405_6456_amd import synth
+from tests.gpu_util import ctx
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def C():
+    c = ctx()
+    yield c
+    c.close()
+
+
+def dev(a, dtype=None):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda:0", dtype=dtype or torch.float64)
+
+
+# ---------------------------------------------------------------- stencil (Eq. FD:Laplacian)
+@pytest.mark.parametrize("nn", [(33, 33, 33), (70, 45, 29), (129, 17, 40), (13, 13, 13)])
+@pytest.mark.parametrize("fdn", [1, 3, 6, 8])
+def test_stencil_fp64_matches_oracle(C, orc, nn, fdn):
+    if min(nn) < 2 * fdn + 1 and fdn > 6:
+        pytest.skip("grid below 2n+1")
+    g = synth.Grid(nn, 0.37, (0.0, 0.0, 0.0))
+    x = synth.random_field(g, 1000 + fdn)
+    ref = orc.laplacian(g, fdn, x)
+    y = C.apply_laplacian(dev(x), g.h, fdn).cpu().numpy()
+    scale = np.abs(ref).max()
+    assert np.abs(y - ref).max() <= 1e-13 * scale
+
+
+@pytest.mark.parametrize("nn", [(33, 33, 33), (70, 45, 29)])
+def test_stencil_fp32_matches_oracle(C, orc, nn):
+    import torch
+
+    g = synth.Grid(nn, 0.5, (0.0, 0.0, 0.0))
+    x = synth.random_field(g, 7).astype(np.float32)
+    ref = orc.laplacian(g, 6, x.astype(np.float64))
+    y = C.apply_laplacian(dev(x, torch.float32), g.h, 6).cpu().numpy().astype(np.float64)
+    # 37 float products and sums: a few ulp of the largest partial sums
+    assert np.abs(y - ref).max() <= 2e-6 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("tuning", [0, 1, 2, 3, 4])
+def test_stencil_tile_variants(C, orc, tuning):
+    g = synth.Grid((77, 51, 45), 0.5, (0.0, 0.0, 0.0))
+    x = synth.random_field(g, 3)
+    ref = orc.laplacian(g, 6, x)
+    C.set_tuning(tuning, 1024, 4)
+    try:
+        y = C.apply_laplacian(dev(x), g.h, 6).cpu().numpy()
+    finally:
+        C.set_tuning(3, 1024, 4)
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_stencil_full_size_185(C, orc):
+    # the largest workload's grid (185^3), in the launch configuration the solver uses
+    g = synth.Grid((185, 185, 185), 0.5, (0.0, 0.0, 0.0))
+    x = synth.random_field(g, 5)
+    ref = orc.laplacian(g, 6, x)
+    y = C.apply_laplacian(dev(x), g.h, 6).cpu().numpy()
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_stencil_polynomial_exact(C):
+    # x^a y^b z^c (exponents <= 13) is differentiated exactly away from the boundary
+    nn, h, n = (40, 36, 33), 0.3, 6
+    o = [-0.5 * (m - 1) * h for m in nn]
+    z, y, x = np.meshgrid(*[o[a] + h * np.arange(nn[a]) for a in (2, 1, 0)], indexing="ij")
+    f = x ** 7 * y ** 4 * z ** 2
+    exact = 42 * x ** 5 * y ** 4 * z ** 2 + 12 * x ** 7 * y ** 2 * z ** 2 + 2 * x ** 7 * y ** 4
+    lap = C.apply_laplacian(dev(f), h, n).cpu().numpy()
+    sl = (slice(n, nn[2] - n), slice(n, nn[1] - n), slice(n, nn[0] - n))
+    assert np.abs(lap[sl] - exact[sl]).max() <= 1e-9 * np.abs(exact[sl]).max()
+
+
+# ---------------------------------------------------------------- Poisson (Eq. Poisson:Discretized)
+def _gauss_rho(g, charges):
+    z, y, x = np.meshgrid(*[g.origin[a] + g.h * np.arange(g.n[a]) for a in (2, 1, 0)], indexing="ij")
+    rho = np.zeros(g.shape)
+    for q, c, s in charges:
+        r2 = (x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2
+        rho += q * math.pi ** -1.5 / s ** 3 * np.exp(-r2 / s ** 2)
+    return rho
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_poisson_matches_oracle(C, orc, bc, precision):
+    g = synth.Grid((41, 38, 35), 0.45, (-9.0, -8.3, -7.6))
+    rho = _gauss_rho(g, [(1.0, (0.3, -0.4, 0.2), 1.0), (-0.7, (-1.1, 0.8, -0.3), 0.9)])
+    rhs = orc.poisson_rhs(g, 6, bc, rho)
+    ref, _, _, _ = orc.poisson_cg(g, 6, rhs, tol=1e-13)
+    phi, its, rel = C.poisson(dev(rho), g, bc=bc, precision=precision, tol=1e-11)
+    assert rel < 1e-11
+    assert np.abs(phi.cpu().numpy() - ref).max() <= 1e-8 * np.abs(ref).max()
+
+
+def test_poisson_gaussian_closed_form(C):
+    from scipy.special import erf
+
+    s, h, n = 1.5, 0.25, 57
+    o = -0.5 * (n - 1) * h
+    g = synth.Grid((n, n, n), h, (o, o, o))
+    rho = _gauss_rho(g, [(1.0, (0, 0, 0), s)])
+    phi, _, rel = C.poisson(dev(rho), g, bc=1, tol=1e-12)
+    z, y, x = np.meshgrid(*[o + h * np.arange(n)] * 3, indexing="ij")
+    r = np.sqrt(x * x + y * y + z * z)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        exact = np.where(r == 0, 2 / (s * math.sqrt(math.pi)), erf(r / s) / r)
+    assert np.abs(phi.cpu().numpy() - exact).max() < 1e-7
+
+
+def test_poisson_warm_start_from_solution(C, orc):
+    # restarting from a converged solution needs at most a couple of iterations (the
+    # recomputed residual differs from the recursively updated one by rounding)
+    g = synth.Grid((33, 33, 33), 0.5, (-8.0, -8.0, -8.0))
+    rho = _gauss_rho(g, [(1.0, (0.2, 0.1, -0.3), 1.0)])
+    phi, its, rel = C.poisson(dev(rho), g, bc=1, tol=1e-10)
+    phi2, its2, rel2 = C.poisson(dev(rho), g, phi0=phi, bc=1, tol=1e-10)
+    assert its > 50 and its2 <= 3 and rel2 < 1e-10
+
+
+def test_poisson_zero_rhs(C):
+    g = synth.Grid((21, 21, 21), 0.5, (0.0, 0.0, 0.0))
+    import torch
+
+    phi, its, rel = C.poisson(torch.zeros(g.shape, dtype=torch.float64, device="cuda:0"), g,
+                              phi0=torch.ones(g.shape, dtype=torch.float64, device="cuda:0"), bc=0)
+    assert its == 0 and float(phi.abs().max()) == 0.0
+
+
+# ---------------------------------------------------------------- nuclei
+@pytest.mark.parametrize("name", ["single", "fcc2"])
+def test_pseudocharge_and_self_energy(C, orc, name):
+    S = synth.config(name)
+    b, es = C.pseudocharge(S)
+    ref = orc.pseudocharge(S)
+    assert np.abs(b.cpu().numpy() - ref).max() <= 1e-14 * np.abs(ref).max()
+    assert abs(es - orc.self_energy(S)) <= 1e-11 * abs(es)
+
+
+def test_pseudocharge_full_size_sampled(C, orc):
+    S = synth.config("fcc10")
+    b, _ = C.pseudocharge(S)
+    b = b.cpu().numpy()
+    nodes = (synth.stream(5, 600).reshape(200, 3) * 185).astype(int)
+    for i, j, k in nodes:
+        assert abs(b[k, j, i] - orc.pseudocharge_at(S, i, j, k)) <= 1e-15 + 1e-13 * abs(b[k, j, i])
+    # neutrality of the whole cluster: h^3 sum b = -sum Z
+    assert abs(S.grid.h ** 3 * b.sum() + S.Z.sum()) < 1e-7 * S.Z.sum()
+
+
+@pytest.mark.parametrize("name", ["single", "fcc2"])
+def test_forces_given_phi(C, orc, name):
+    S = synth.config(name)
+    g = S.grid
+    phi = 0.3 * synth.random_field(g, 17) + 1.0
+    f_gpu = C.forces(S, None, dev(phi))
+    f_ref = orc.forces(S, orc.params(), phi)
+    assert np.abs(f_gpu - f_ref).max() <= 1e-10 * max(1.0, np.abs(f_ref).max())
+
+
+# ---------------------------------------------------------------- energy and residual
+@pytest.mark.parametrize("name", ["single", "fcc2"])
+@pytest.mark.parametrize("bc", [0, 1])
+def test_energy_gradient_matches_oracle(C, orc, name, bc):
+    import paper_1405_6456_amd as lib
+
+    S = synth.config(name)
+    u = synth.initial_u(S.grid, S.N)
+    eta, mu = -0.17, 0.8
+    g_ref, e_ref, phi_ref, _ = orc.evaluate(S, orc.params(bc=bc, tol_poisson=1e-12), u, eta, mu)
+    g, e, phi = C.energy_gradient(S, lib.default_params(phi_bc=bc, tol_poisson=1e-12), dev(u), eta, mu)
+    assert np.abs(phi.cpu().numpy() - phi_ref).max() <= 1e-8 * np.abs(phi_ref).max()
+    assert np.abs(g.cpu().numpy() - g_ref).max() <= 1e-8 * np.abs(g_ref).max()
+    for k in ("E_TF", "E_vW", "E_xc", "E_es", "E_total", "C", "L"):
+        kk = "C_h" if k == "C" else k
+        assert abs(e[kk] - e_ref[k]) <= 1e-9 * max(1.0, abs(e_ref[k])), k
