@@ -1,0 +1,202 @@
+"""Benchmark: one step = one full ground-state solve of a synthetic Al-like fcc cluster.
+
+Workload (default): 10x10x10 conventional fcc cells, 4000 atoms, a = 7.6 Bohr,
+seeded 0.1 Bohr displacements, 8 Bohr vacuum, h = 0.5 Bohr (185^3 nodes), order-12
+stencil, Gaussian pseudocharge (Z = 3, s = 1), TFW + LDA, AL outer loop (eta0 -0.2,
+mu0 1, kappa 0.1), tolerances 1e-8 / 1e-6 / 1e-10.  The timed path solves Poisson
+with FP32 stencil/CG vectors inside FP64 iterative refinement; the plain FP64 GPU
+path is timed once afterwards on the same input for the speedup and the error.
+
+Prints one JSON line.  value = stencil grid-point updates per second over the whole
+solve: (FP64 + FP32 stencil applications) x nodes / wall time of the timed steps.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="fcc10", choices=["single", "fcc2", "fcc5", "fcc10"])
+    ap.add_argument("--precision", default="fp32r", choices=["fp32r", "fp64"])
+    ap.add_argument("--no-fp64-ref", action="store_true", help="skip the FP64 comparison solve")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
+    ap.add_argument("--sample-every", type=int, default=8, help="CG kernel launches per timed sample")
+    ap.add_argument("--mode", default="solve", choices=["solve", "stencil"],
+                    help="stencil: only the streaming stencil measurement (for counter profiling)")
+    return ap.parse_args()
+
+
+def traffic_for(kernel_key):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    src = os.path.join(ROOT, "paper_1405_6456_amd", "csrc", "kernels.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    ent = data.get(kernel_key)
+    if not ent or ent.get("kernels_sha256_16") != digest:
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(system, seconds):
+    """The oracle's conjugate-gradient Poisson iterations on the same workload's grid and
+    right-hand side (u0^2 + b with the multipole boundary values), as stencil point
+    updates per second; the iteration count is chosen to take about `seconds`."""
+    import numpy as np
+
+    import oracle
+    from paper_1405_6456_amd import synth
+
+    u0 = synth.initial_u(system.grid, system.N)
+    b = oracle.pseudocharge(system)
+    rhs = oracle.poisson_rhs(system.grid, 6, 1, u0 * u0 + b)
+    t = time.perf_counter()
+    _, it1, _, _ = oracle.poisson_cg(system.grid, 6, rhs, tol=1e-300, maxit=2)
+    per = (time.perf_counter() - t) / 3.0  # initial residual + 2 iterations
+    iters = max(2, int(seconds / max(per, 1e-6)))
+    t = time.perf_counter()
+    _, it, _, _ = oracle.poisson_cg(system.grid, 6, rhs, tol=1e-300, maxit=iters)
+    dt = time.perf_counter() - t
+    pts = system.grid.npts
+    return {"value": (it + 1) * pts / dt / 1e9, "unit": "Gpts/s", "cores": oracle.get_threads(), "kind": "oracle",
+            "sample": f"oracle CG Poisson on the {system.name} grid ({pts} nodes), {it} iterations + initial "
+                      f"residual in {dt:.1f} s (stencil point updates per second of the same operator)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the solve is not sharded across GPUs)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1405_6456_amd as lib
+    from paper_1405_6456_amd import synth
+
+    torch.cuda.set_device(0)
+    S = synth.config(args.workload)
+    if args.mode == "stencil":
+        ctx = lib.Context(0)
+        for dt in (0, 1):
+            ms = ctx.bench_stencil(S.grid.n, 6, dt, reps=20, nbuf=6)
+            es = 8 if dt == 0 else 4
+            print(json.dumps({"stencil": "f64" if dt == 0 else "f32", "nodes": S.grid.npts, "ms": ms,
+                              "gpts": S.grid.npts / (ms * 1e-3) / 1e9,
+                              "hbm_frac": S.grid.npts * 2 * es / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}), flush=True)
+        # reference copy of a known size (2 x 256 MiB moved), to scale the HBM byte counters
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"reference_copy_bytes_read": src.numel() * 8, "bytes_written": dst.numel() * 8}),
+              flush=True)
+        ctx.close()
+        return
+    u0 = synth.initial_u(S.grid, S.N)
+    prec = lib.FP32_REFINED if args.precision == "fp32r" else lib.FP64
+    prm = lib.default_params(precision=prec)
+    ctx = lib.Context(0)
+    npts = S.grid.npts
+
+    for _ in range(args.warmup):
+        ctx.solve(S, prm, u0, want_fields=False, want_forces=True)
+
+    ctx.profile_cg_kernel(args.sample_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [ctx.solve(S, prm, u0, want_fields=False, want_forces=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dt_idx = 1 if prec == lib.FP32_REFINED else 0
+    launches, mean_ms, kpts = ctx.cg_kernel_stats(dt_idx)
+    ctx.profile_cg_kernel(0)
+
+    last = outs[-1]
+    mv = sum(o["matvec_fp64"] + o["matvec_fp32"] for o in outs)
+    ms_per_step = 1e3 * wall / args.steps
+    value = mv * npts / wall / 1e9
+    esize = 4 if prec == lib.FP32_REFINED else 8
+    # algorithmic bytes of the CG stencil kernel per node: read r and p, write p and A p
+    alg_bytes = 4 * esize * kpts
+    achieved = alg_bytes / (mean_ms * 1e-3) / 1e9 if mean_ms > 0 else 0.0
+    kernel_key = f"cg_stencil_{'f32' if esize == 4 else 'f64'}_{args.workload}"
+    tr = traffic_for(kernel_key)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
+                "kernel": "k_stencil CG pass (p = r + beta p, A p, p.Ap)",
+                "alg_bytes_per_launch": alg_bytes, "mean_launch_ms": round(mean_ms, 5), "timed_launches": launches}
+
+    # streaming stencil throughput (six rotating buffer pairs, more than the 256 MB cache)
+    st_ms = ctx.bench_stencil(S.grid.n, 6, 1 if esize == 4 else 0, reps=100, nbuf=6)
+    stencil = {"gpts": round(npts / (st_ms * 1e-3) / 1e9, 1),
+               "hbm_frac": round(npts * 2 * esize / (st_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               "dtype": "f32" if esize == 4 else "f64"}
+
+    extra = {}
+    if not args.no_fp64_ref and prec == lib.FP32_REFINED:
+        t = time.perf_counter()
+        ref = ctx.solve(S, lib.default_params(precision=lib.FP64), u0, want_fields=False, want_forces=True)
+        t64 = time.perf_counter() - t
+        extra["fp64_path"] = {"ms_per_solve": round(1e3 * t64, 1), "status": ref["status"],
+                              "cg_iters": ref["cg_iters"], "E_total": ref["E_total"]}
+        extra["speedup_vs_fp64"] = round(t64 / (wall / args.steps), 3)
+        extra["err_vs_fp64"] = {"E_per_atom": abs(last["E_total"] - ref["E_total"]) / S.M,
+                                "F_max": float(np.abs(last["forces"] - ref["forces"]).max())}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(S, args.cpu_seconds)
+
+    line = {
+        "metric": "Gpts/s stencil (%HBM peak); AL-OFDFT solves/s, p50/p99 latency vs FP64",
+        "value": round(value, 2),
+        "unit": "Gpts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 stencil/CG + f64 refinement" if prec == lib.FP32_REFINED else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{S.name}: {S.M} atoms, {S.grid.n[0]}^3 nodes, h={S.grid.h}, order 12, "
+                               f"{'FP32+FP64-refined' if prec == lib.FP32_REFINED else 'FP64'} Poisson",
+                   "atoms": S.M, "nodes": npts, "parallelism": "single GPU"},
+        "solves_per_s": round(args.steps / wall, 4),
+        "status": last["status"],
+        "E_total": last["E_total"],
+        "counts": {k: last[k] for k in ("outer", "inner", "grad_evals", "poisson_solves", "cg_iters", "matvec_fp64",
+                                        "matvec_fp32", "refinements")},
+        "stencil_streaming": stencil,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -209,13 +209,27 @@ int alofdft_forces(alofdft_ctx* ctx, const alofdft_system* sys, const alofdft_pa
 int alofdft_bench_stencil(alofdft_ctx* ctx, const int n[3], int fd_half_width, int dtype, int reps, int nbuf,
                           double* ms_per_apply);
 
-/* Launch tuning of a context: stencil tile variant (0..4: 64x8, 64x16, 32x16,
- * 64x8 with one row per thread, 64x8 with four rows per thread; x by y, in
- * nodes, for the order-12 stencil), the target number of stencil workgroups
- * (z chunking), and the FP32 inner-solve residual reduction 10^-inner_tol_exp
- * of the refined Poisson solve (1..7).  Defaults 3, 1024, 4.  INVALID_ARGUMENT
- * outside those ranges. */
+/* Launch tuning of a context: stencil tile variant for the order-12 stencil (0: 64x8
+ * nodes in x-y, two rows per thread, z column prefetched one plane ahead; 1: 64x4,
+ * one row per thread, three planes ahead; 2: 64x8, one row, one ahead; 3: 64x8, one
+ * row, three ahead; 4: 64x4, one row, one ahead), the target number of stencil
+ * workgroups (sets how many z chunks each XCD gets), and the FP32 inner-solve
+ * residual reduction 10^-inner_tol_exp of the refined Poisson solve (1..7).
+ * Defaults 0, 1024, 4.  INVALID_ARGUMENT outside those ranges. */
 int alofdft_set_tuning(alofdft_ctx* ctx, int stencil_variant, int target_blocks, int inner_tol_exp);
+
+/* Measurement of the dominant kernel.  With sample_every > 0, every
+ * sample_every-th launch of the conjugate-gradient stencil kernel (the fused
+ * p = r + beta p, A p and p.Ap pass of each CG iteration) is bracketed by HIP
+ * events on the context stream; launches made after a solve has converged (which
+ * exit at once) are not counted.  sample_every = 0 stops sampling.  Calling it
+ * resets the statistics.  INVALID_ARGUMENT for a null context or a negative value. */
+int alofdft_profile_cg_kernel(alofdft_ctx* ctx, int sample_every);
+
+/* Statistics of the sampled launches for dtype 0 (FP64 CG) or 1 (FP32 inner CG of
+ * the refined solve): number of timed launches, mean duration in ms, and the grid
+ * points (n[0]*n[1]*n[2]) of the last timed launch.  All three pointers required. */
+int alofdft_cg_kernel_stats(alofdft_ctx* ctx, int dtype, long long* launches, double* mean_ms, long long* points);
 
 #ifdef __cplusplus
 }

@@ -630,8 +630,19 @@ static int nlcg(Work& W, double* u, double eta, double mu, OrEnergies* e_out, do
     double t_prev = 0.0, s_prev = slope0;
     double t_cur = P->sigma0;
     double s_cur = trial(t_cur);
-    if (s_cur > 0.0) b = t_cur; else a = t_cur;
-    for (int j = 0; j < P->max_secant; ++j) {
+    // a trial with a non-finite slope or L overshot: it closes the bracket from above
+    auto bad = [&]() { return !std::isfinite(s_cur) || !std::isfinite(e.L); };
+    if (s_cur > 0.0 || bad()) b = t_cur; else a = t_cur;
+    for (int j = 0; j < P->max_secant || bad(); ++j) {
+      if (bad()) {
+        if (j > 60) break;
+        t_prev = a;
+        s_prev = slope0;
+        t_cur = 0.5 * (a + b);
+        s_cur = trial(t_cur);
+        if (s_cur > 0.0 || bad()) b = t_cur; else a = t_cur;
+        continue;
+      }
       if (std::fabs(s_cur) <= P->secant_rel * std::fabs(slope0)) break;
       double curv = (s_cur - s_prev) / (t_cur - t_prev);
       double t_new = (curv > 0.0) ? t_cur - s_cur / curv : NAN;
@@ -643,7 +654,11 @@ static int nlcg(Work& W, double* u, double eta, double mu, OrEnergies* e_out, do
       s_cur = trial(t_cur);
       if (P->verbose > 2)
         std::printf("      secant j=%d t=%.4e slope=%.4e slope0=%.4e [a=%.3e b=%.3e]\n", j, t_cur, s_cur, slope0, a, b);
-      if (s_cur > 0.0) b = std::min(b, t_cur); else a = std::max(a, t_cur);
+      if (s_cur > 0.0 || bad()) b = std::min(b, t_cur); else a = std::max(a, t_cur);
+    }
+    if (bad()) {  // no finite point found along d
+      status = -4;
+      break;
     }
     gn = hnorm(W, g.data());
     // Polak-Ribiere update with s = M^-1 r, r = -g

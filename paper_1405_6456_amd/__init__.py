@@ -95,6 +95,8 @@ def lib():
         L.alofdft_pseudocharge.argtypes = [_VP, C.POINTER(SystemS), C.POINTER(Params), _VP, _DP]
         L.alofdft_forces.argtypes = [_VP, C.POINTER(SystemS), C.POINTER(Params), _VP, _DP]
         L.alofdft_bench_stencil.argtypes = [_VP, C.POINTER(C.c_int), C.c_int, C.c_int, C.c_int, C.c_int, _DP]
+        L.alofdft_profile_cg_kernel.argtypes = [_VP, C.c_int]
+        L.alofdft_cg_kernel_stats.argtypes = [_VP, C.c_int, C.POINTER(C.c_longlong), _DP, C.POINTER(C.c_longlong)]
         _lib = L
     return _lib
 
@@ -266,6 +268,16 @@ class Context:
         _check(self, lib().alofdft_forces(self.handle, C.byref(S.s), C.byref(params), _ptr(phi),
                                           f.ctypes.data_as(_DP)))
         return f
+
+    def profile_cg_kernel(self, sample_every=1):
+        """Start (reset) sampled HIP-event timing of the CG stencil kernel; 0 stops it."""
+        _check(self, lib().alofdft_profile_cg_kernel(self.handle, int(sample_every)))
+
+    def cg_kernel_stats(self, dtype=0):
+        """(timed launches, mean ms per launch, grid points per launch) for dtype 0 (FP64) / 1 (FP32)."""
+        n, ms, pts = C.c_longlong(), C.c_double(), C.c_longlong()
+        _check(self, lib().alofdft_cg_kernel_stats(self.handle, dtype, C.byref(n), C.byref(ms), C.byref(pts)))
+        return n.value, ms.value, pts.value
 
     def bench_stencil(self, n, fd_half_width=6, dtype=0, reps=100, nbuf=6):
         """Mean kernel time (ms) of one stencil application over a rotation of nbuf buffer pairs."""

@@ -16,11 +16,13 @@
 #include <functional>
 #include <map>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/alofdft.h"
 #include "common.h"
-#include "kernels.hip"
+#include "kernels_misc.h"
+#include "launch.h"
 
 using namespace alofdft;
 
@@ -31,11 +33,17 @@ struct alofdft_ctx {
   std::map<std::string, std::pair<void*, size_t>> bufs;
   double* pin = nullptr;  // pinned host scalars
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  int variant = 3;        // stencil tile variant
+  int variant = 0;        // stencil tile variant
   int target_blocks = 1024;
   int inner_tol_exp = 4;  // FP32 inner CG reduces the residual by 10^-inner_tol_exp
   // geometry each padded work array was last zeroed for (its halo is zero only then)
   std::map<std::string, std::string> geom_key;
+  // sampled event timing of the CG stencil kernel (index 0: FP64, 1: FP32)
+  int prof_every = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pool;
+  long long prof_count[2] = {0, 0};
+  double prof_ms[2] = {0.0, 0.0};
+  long long prof_points[2] = {0, 0};
 };
 
 namespace {
@@ -158,55 +166,26 @@ int launch_pw(alofdft_ctx* c, const Geom& g, const Op& op) {
   return nb;
 }
 
-template <typename T, int R, int BX, int BY, int VY, class Op>
-int launch_cfg(alofdft_ctx* c, const Geom& g, const StencilW<T>& W, const Op& op) {
-  const int tiles_x = (g.nx + BX - 1) / BX;
-  const int tiles_y = (g.ny + BY * VY - 1) / (BY * VY);
-  const int tiles = tiles_x * tiles_y;
-  int nchunks = std::max(1, (c->target_blocks + tiles - 1) / tiles);
-  int zc = std::max((g.nz + nchunks - 1) / nchunks, std::min(g.nz, 2 * R + 2));
-  nchunks = (g.nz + zc - 1) / zc;
-  const int nb = tiles * nchunks;
-  hipLaunchKernelGGL((k_stencil<T, R, BX, BY, VY, Op>), dim3(nb), dim3(BX * BY), 0, c->stream, g, W, zc, tiles_x,
-                     tiles_y, op);
-  CHECK_LAUNCH(c);
-  return nb;
-}
-
-// Largest number of blocks any stencil launch can use (partials buffers are sized by it).
-int max_stencil_blocks(const Geom& g, int target) {
-  const int tiles = ((g.nx + 31) / 32) * ((g.ny + 7) / 8);
-  return tiles * std::max(1, (target + tiles - 1) / tiles) + tiles * 4 + 64;
-}
-
-template <typename T, int R, class Op>
-int launch_r(alofdft_ctx* c, const Geom& g, const StencilW<T>& W, const Op& op) {
-  if constexpr (R == 6) {
-    switch (c->variant) {
-      case 1: return launch_cfg<T, R, 64, 4, 4, Op>(c, g, W, op);
-      case 2: return launch_cfg<T, R, 32, 8, 2, Op>(c, g, W, op);
-      case 3: return launch_cfg<T, R, 64, 8, 1, Op>(c, g, W, op);
-      case 4: return launch_cfg<T, R, 64, 2, 4, Op>(c, g, W, op);
-      default: break;
-    }
-  }
-  return launch_cfg<T, R, 64, 4, 2, Op>(c, g, W, op);
-}
-
 template <typename T, class Op>
 int launch_stencil(alofdft_ctx* c, const Geom& g, const StencilW<T>& W, const Op& op) {
+  const LaunchCfg lc{c->stream, c->variant, c->target_blocks};
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
   switch (g.R) {
-    case 1: return launch_r<T, 1>(c, g, W, op);
-    case 2: return launch_r<T, 2>(c, g, W, op);
-    case 3: return launch_r<T, 3>(c, g, W, op);
-    case 4: return launch_r<T, 4>(c, g, W, op);
-    case 5: return launch_r<T, 5>(c, g, W, op);
-    case 6: return launch_r<T, 6>(c, g, W, op);
-    case 7: return launch_r<T, 7>(c, g, W, op);
-    case 8: return launch_r<T, 8>(c, g, W, op);
+    case 1: e = launch_stencil_r<1>(lc, g, W, op, &nb); break;
+    case 2: e = launch_stencil_r<2>(lc, g, W, op, &nb); break;
+    case 3: e = launch_stencil_r<3>(lc, g, W, op, &nb); break;
+    case 4: e = launch_stencil_r<4>(lc, g, W, op, &nb); break;
+    case 5: e = launch_stencil_r<5>(lc, g, W, op, &nb); break;
+    case 6: e = launch_stencil_r<6>(lc, g, W, op, &nb); break;
+    case 7: e = launch_stencil_r<7>(lc, g, W, op, &nb); break;
+    case 8: e = launch_stencil_r<8>(lc, g, W, op, &nb); break;
+    default:
+      set_err(c, "fd_half_width %d out of range", g.R);
+      throw Fail{ALOFDFT_INVALID_ARGUMENT};
   }
-  set_err(c, "fd_half_width %d out of range", g.R);
-  throw Fail{ALOFDFT_INVALID_ARGUMENT};
+  HIPC(c, e);
+  return nb;
 }
 
 void finalize(alofdft_ctx* c, const double* parts, int nparts, int nred, double scale, double* out) {
@@ -276,6 +255,25 @@ struct AddFloatOp {  // x64 += (double) x32
   __device__ void apply(long long i, int, int, int, double*) const { x64[i] += (double)x32[i]; }
 };
 
+// out = c0 a + c1 b + c2 c over the interior (b, c nullable when their coefficient is 0).
+struct CombineOp {
+  static constexpr int NRED = 0;
+  double* out;
+  const double* a;
+  const double* b;
+  const double* c;
+  double c0, c1, c2;
+  double* parts_out;
+  template <int NT>
+  __device__ bool begin() { return true; }
+  __device__ void apply(long long i, int, int, int, double*) const {
+    double v = c0 * a[i];
+    if (b) v += c1 * b[i];
+    if (c) v += c2 * c[i];
+    out[i] = v;
+  }
+};
+
 // ----------------------------------------------------------------- Poisson CG
 struct CGResult {
   long long iters = 0;
@@ -313,13 +311,44 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
   int nred_prev = 2;
   CGResult res;
   const double tol2 = tol * tol;
+  const int pi = sizeof(T) == 8 ? 0 : 1;
+  // sampled launches: (iteration, event pair index); pairs are read back at the
+  // next host synchronisation and kept only for iterations before convergence
+  std::vector<std::pair<long long, size_t>> pending;
+  size_t pool_used = 0;
+  auto harvest = [&](long long stop_iter) {
+    for (auto& pe : pending) {
+      if (pe.first >= stop_iter) continue;
+      float ms = 0.f;
+      HIPC(c, hipEventElapsedTime(&ms, c->prof_pool[pe.second].first, c->prof_pool[pe.second].second));
+      c->prof_ms[pi] += ms;
+      c->prof_count[pi]++;
+      c->prof_points[pi] = (long long)g.nx * g.ny * g.nz;
+    }
+    pending.clear();
+    pool_used = 0;
+  };
   long long k = 0;
   for (;; ++k) {
     if (k >= max_it) break;
     T* pold = (k & 1) ? p1 : p0;
     T* pnew = (k & 1) ? p0 : p1;
     CGP1Op<T> op1{r, pold, pnew, Ap, st, prev, nprev, nred_prev, (int)k, tol2, partsA, T(0)};
+    const bool timed = c->prof_every > 0 && k % c->prof_every == 0;
+    if (timed) {
+      if (pool_used == c->prof_pool.size()) {
+        hipEvent_t a, b;
+        HIPC(c, hipEventCreate(&a));
+        HIPC(c, hipEventCreate(&b));
+        c->prof_pool.push_back({a, b});
+      }
+      HIPC(c, hipEventRecord(c->prof_pool[pool_used].first, c->stream));
+    }
     const int nb1 = launch_stencil(c, g, A, op1);
+    if (timed) {
+      HIPC(c, hipEventRecord(c->prof_pool[pool_used].second, c->stream));
+      pending.push_back({k, pool_used++});
+    }
     CGP2Op<T> op2{x, r, pnew, Ap, st, partsA, nb1, (int)k, partsB, T(0)};
     nprev = launch_pw(c, g, op2);
     prev = partsB;
@@ -327,13 +356,16 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
     if ((k + 1) % check_every == 0) {
       HIPC(c, hipMemcpyAsync(c->pin, st, sizeof(CGState), hipMemcpyDeviceToHost, c->stream));
       sync(c);
-      if (((CGState*)c->pin)->done) break;
+      const CGState* sp = (CGState*)c->pin;
+      harvest(sp->done ? sp->iter : k + 1);
+      if (sp->done) break;
     }
   }
   // one more half iteration to test the last residual if the loop ended without a verdict
   HIPC(c, hipMemcpyAsync(c->pin, st, sizeof(CGState), hipMemcpyDeviceToHost, c->stream));
   sync(c);
   CGState s = *(CGState*)c->pin;
+  harvest(s.done ? s.iter : k);
   if (!s.done && k < max_it + 1) {
     T* pold = (k & 1) ? p1 : p0;
     T* pnew = (k & 1) ? p0 : p1;
@@ -606,6 +638,7 @@ class Solver {
     b_ = bufT<double>(c, "s.b", T);
     phi_ = bufT<double>(c, "s.phi", T);
     rhs_ = bufT<double>(c, "s.rhs", T);
+    for (int i = 0; i < 3; ++i) ph_[i] = bufT<double>(c, "s.ph" + std::to_string(i), T);
     partsU_ = bufT<double>(c, "s.partsU", (size_t)kPointwiseBlocks * kUpdRed);
     partsG_ = bufT<double>(c, "s.partsG", (size_t)max_stencil_blocks(g_, c->target_blocks) * G_NRED);
     scal_ = bufT<double>(c, "s.scal", kUpdRed + G_NRED + 8);
@@ -622,7 +655,7 @@ class Solver {
 
   // Zero all work arrays (halo included) and set up the nuclei.
   void setup(const double* u0_dense_dev, bool u0_abs) {
-    for (double* a : {us_, v_, d_, sa_, sb_, b_, phi_, rhs_}) fill<double>(c_, a, g_.total, 0.0);
+    for (double* a : {us_, v_, d_, sa_, sb_, b_, phi_, rhs_, ph_[0], ph_[1], ph_[2]}) fill<double>(c_, a, g_.total, 0.0);
     at_ = upload_atoms(c_, S_, P_->r_cut);
     pseudocharge_dev(c_, g_, S_, at_, P_->gauss_width, P_->r_cut, b_);
     std::vector<double> self;
@@ -635,7 +668,13 @@ class Solver {
 
   // Evaluate at v = u_start + t d (trial) or with the direction update fused (dir).
   void eval_trial(double t, double eta, double mu, bool with_dir, double beta, Eval& ev) {
+    bad_ = false;
     if (with_dir) {
+      // new line: phi of the start point (t = 0) opens the history
+      CombineOp cp{ph_[0], phi_, nullptr, nullptr, 1.0, 0.0, 0.0, nullptr};
+      launch_pw(c_, g_, cp);
+      th_[0] = 0.0;
+      nh_ = 1;
       DirOp op{us_, d_, s_new(), v_, b_, beta, t, frame_, partsU_};
       nU_ = launch_pw(c_, g_, op);
       std::swap(s_cur_, s_prev_);  // the s just used becomes s_old of the next gradient
@@ -643,7 +682,21 @@ class Solver {
       TrialOp op{us_, d_, b_, v_, t, frame_, partsU_};
       nU_ = launch_pw(c_, g_, op);
     }
+    if (nh_ >= 2) {
+      // Lagrange interpolation of phi(t) through the solved points of this line
+      double L[3] = {1.0, 1.0, 1.0};
+      for (int i = 0; i < nh_; ++i)
+        for (int j = 0; j < nh_; ++j)
+          if (i != j) L[i] *= (t - th_[j]) / (th_[i] - th_[j]);
+      CombineOp cp{phi_, ph_[0], ph_[1], nh_ > 2 ? ph_[2] : nullptr, L[0], L[1], nh_ > 2 ? L[2] : 0.0, nullptr};
+      launch_pw(c_, g_, cp);
+    }
     eval_at_v(eta, mu, ev);
+    if (!bad_ && nh_ >= 1 && nh_ < 3) {
+      CombineOp cp{ph_[nh_], phi_, nullptr, nullptr, 1.0, 0.0, 0.0, nullptr};
+      launch_pw(c_, g_, cp);
+      th_[nh_++] = t;
+    }
   }
 
   void eval_at_v(double eta, double mu, Eval& ev) {
@@ -669,8 +722,18 @@ class Solver {
     counts_.refinements += ps.refinements;
     relres_ = ps.relres;
     if (ps.status == ALOFDFT_NUMERICAL) {
-      set_err(c_, "non-finite value in the Poisson solve");
-      throw Fail{ALOFDFT_NUMERICAL};
+      // a non-finite charge: report the trial as non-finite; phi is reset to the
+      // potential at the start of the line (or zero) so later solves start clean
+      bad_ = true;
+      if (nh_ >= 1) {
+        CombineOp cp{phi_, ph_[0], nullptr, nullptr, 1.0, 0.0, 0.0, nullptr};
+        launch_pw(c_, g_, cp);
+      } else {
+        fill<double>(c_, phi_, g_.total, 0.0);
+      }
+      for (int i = 0; i < G_NRED; ++i) ev.gr[i] = NAN;
+      for (int i = 0; i < kUpdRed; ++i) ev.upd[i] = NAN;
+      return;
     }
     if (ps.status == ALOFDFT_NOT_CONVERGED) poisson_capped_ = true;
     GradOp gop{v_, phi_, b_, d_, s_old(), s_new(), gout_, upd, 0.5 * P_->lambda, eta, mu > 0 ? 1.0 / mu : 0.0,
@@ -688,10 +751,15 @@ class Solver {
     counts_.grad_evals++;
     counts_.matvec_fp64++;
     for (int i = 0; i < G_NRED; ++i)
-      if (!std::isfinite(ev.gr[i])) {
-        set_err(c_, "non-finite value in the residual evaluation");
-        throw Fail{ALOFDFT_NUMERICAL};
-      }
+      if (!std::isfinite(ev.gr[i])) bad_ = true;
+  }
+
+  // Evaluation that must be finite (start point, new outer step, single evaluations).
+  void require_finite(const char* what) {
+    if (bad_) {
+      set_err(c_, "non-finite value in %s", what);
+      throw Fail{ALOFDFT_NUMERICAL};
+    }
   }
 
   double C_of(const Eval& e) const { return e.upd[0] - S_->N_elec; }
@@ -749,8 +817,19 @@ class Solver {
       eval_trial(t_cur, eta, mu, true, bet, ev);
       double s_cur = ev.gr[G_SLOPE];
       double a = 0.0, b = INFINITY, t_prev = 0.0, s_prev = slope0;
-      if (s_cur > 0.0) b = t_cur; else a = t_cur;
-      for (int j = 0; j < P_->max_secant; ++j) {
+      // a non-finite trial overshot: it closes the bracket from above
+      if (s_cur > 0.0 || bad_) b = t_cur; else a = t_cur;
+      for (int j = 0; j < P_->max_secant || bad_; ++j) {
+        if (bad_) {
+          if (j > 60) break;
+          t_prev = a;
+          s_prev = slope0;
+          t_cur = 0.5 * (a + b);
+          eval_trial(t_cur, eta, mu, false, 0.0, ev);
+          s_cur = ev.gr[G_SLOPE];
+          if (s_cur > 0.0 || bad_) b = t_cur; else a = t_cur;
+          continue;
+        }
         if (std::fabs(s_cur) <= P_->secant_rel * std::fabs(slope0)) break;
         const double curv = (s_cur - s_prev) / (t_cur - t_prev);
         double t_new = curv > 0.0 ? t_cur - s_cur / curv : NAN;
@@ -761,7 +840,11 @@ class Solver {
         t_cur = t_new;
         eval_trial(t_cur, eta, mu, false, 0.0, ev);
         s_cur = ev.gr[G_SLOPE];
-        if (s_cur > 0.0) b = std::min(b, t_cur); else a = std::max(a, t_cur);
+        if (s_cur > 0.0 || bad_) b = std::min(b, t_cur); else a = std::max(a, t_cur);
+      }
+      if (bad_) {
+        set_err(c_, "no finite point along the search direction");
+        throw Fail{ALOFDFT_NUMERICAL};
       }
       cur = ev;
       gn = std::sqrt(h3_ * cur.gr[G_GG]);
@@ -787,6 +870,7 @@ class Solver {
     double eta = P_->method == ALOFDFT_METHOD_PENALTY ? 0.0 : P_->eta0;
     double mu = P_->mu0;
     eval_trial(0.0, eta, mu, false, 0.0, cur);
+    require_finite("the residual at the initial guess");
     time_setup_ = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     int status = ALOFDFT_NOT_CONVERGED;
     double E_prev = 0.0, gn = 0.0, dE = 0.0, eta_star = eta;
@@ -841,7 +925,10 @@ class Solver {
   void eval_at_v_refresh(double eta, double mu, Eval& cur) {
     TrialOp op{v_, zero_dir(), b_, v_, 0.0, frame_, partsU_};
     nU_ = launch_pw(c_, g_, op);
+    nh_ = 0;
+    bad_ = false;
     eval_at_v(eta, mu, cur);
+    require_finite("the residual at a new outer step");
   }
 
   double* zero_dir() {
@@ -880,6 +967,12 @@ class Solver {
   Geom g_;
   double h3_;
   double *us_, *v_, *d_, *sa_, *sb_, *b_, *phi_, *rhs_, *partsU_, *partsG_, *scal_;
+  // potentials already solved along the current line, for warm starts: the charge
+  // (u_start + t d)^2 + b is quadratic in t (also under |.|), so phi(t) is too
+  double* ph_[3];
+  double th_[3];
+  int nh_ = 0;
+  bool bad_ = false;  // the last evaluation produced a non-finite value
   double* gout_ = nullptr;
   int s_cur_ = 0, s_prev_ = 1;
   int nU_ = 0;
@@ -1044,6 +1137,10 @@ void alofdft_destroy(alofdft_ctx* c) {
   if (c->pin) (void)hipHostFree(c->pin);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  for (auto& pr : c->prof_pool) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
   delete c;
 }
 
@@ -1053,6 +1150,25 @@ int alofdft_set_tuning(alofdft_ctx* c, int stencil_variant, int target_blocks, i
   c->variant = stencil_variant;
   c->target_blocks = target_blocks;
   c->inner_tol_exp = inner_tol_exp;
+  return ALOFDFT_OK;
+}
+
+int alofdft_profile_cg_kernel(alofdft_ctx* c, int sample_every) {
+  if (!c || sample_every < 0) return ALOFDFT_INVALID_ARGUMENT;
+  c->prof_every = sample_every;
+  for (int i = 0; i < 2; ++i) {
+    c->prof_count[i] = 0;
+    c->prof_ms[i] = 0.0;
+    c->prof_points[i] = 0;
+  }
+  return ALOFDFT_OK;
+}
+
+int alofdft_cg_kernel_stats(alofdft_ctx* c, int dtype, long long* launches, double* mean_ms, long long* points) {
+  if (!c || (dtype != 0 && dtype != 1) || !launches || !mean_ms || !points) return ALOFDFT_INVALID_ARGUMENT;
+  *launches = c->prof_count[dtype];
+  *mean_ms = c->prof_count[dtype] ? c->prof_ms[dtype] / c->prof_count[dtype] : 0.0;
+  *points = c->prof_points[dtype];
   return ALOFDFT_OK;
 }
 
@@ -1163,6 +1279,7 @@ int alofdft_energy_gradient(alofdft_ctx* c, const alofdft_system* sys, const alo
     }
     Eval ev;
     S.eval_trial(0.0, eta, mu, false, 0.0, ev);
+    S.require_finite("the residual");
     S.energy(ev, e);
     e->L = e->E_total - eta * e->C_h + (mu > 0 ? e->C_h * e->C_h / (2.0 * mu) : 0.0);
     e->cg_iters = S.counts().cg_iters;

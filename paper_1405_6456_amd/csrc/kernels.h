@@ -4,15 +4,17 @@
 //  * k_stencil: the order-2n star stencil of Eq. FD:Laplacian (Sec. 4).  A block
 //    owns a BX x (BY*VY) tile in x-y and streams a chunk of z planes.  The current
 //    plane, with its x/y halo, is staged in LDS (double buffered, one barrier per
-//    plane); the 2R+1 planes of the z taps stay in registers as a queue of 2R+2
+//    plane); the 2R+1 planes of the z taps stay in registers as a queue of 2R+4
 //    slots that rotates by renaming (the z loop is unrolled over the queue length),
-//    and the next plane is prefetched one step ahead.  The epilogue is an Op
+//    with the z column prefetched three planes ahead and the halo two.  The epilogue is an Op
 //    functor, so the CG update, the residual/energy evaluation and the plain
 //    Laplacian all share one load/stage/compute skeleton.
 //  * k_pointwise: wave-per-row sweeps of the interior for the vector updates, with
 //    deterministic block reductions (wavefront shuffles, then LDS) whose per-block
 //    partials are summed in a fixed order by the consumer.
 //  * per-atom kernels for the pseudocharge ball, self energy and forces.
+#pragma once
+
 #include <cmath>
 
 #include "common.h"
@@ -72,16 +74,26 @@ __device__ inline int xcd_swizzle(int b, int nb) {
 }
 
 // ----------------------------------------------------------------- stencil
-template <typename T, int R, int BX, int BY, int VY, class Op>
+// Software pipeline per z plane (one barrier each).  Own z-columns stream through a
+// register queue of K = 2R+1+PD slots (2R+1 taps in use, PD planes in flight), the
+// x/y halo through HS register sets (HS planes ahead), then the plane is staged in
+// one of two LDS buffers.  DEEP = false: PD = 1, HS = 1; DEEP = true: PD = 3, HS = 2.
+// The y taps that fall on this thread's own rows come from the queue, the rest from
+// LDS.  Every global load is limited to planes zbeg-R .. zend-1+R of the chunk, which
+// the padded layout holds.
+template <typename T, int R, int BX, int BY, int VY, bool DEEP, class Op>
 __global__ void __launch_bounds__(BX* BY) k_stencil(Geom g, StencilW<T> W, int zc, int tiles_x, int tiles_y, Op op) {
   constexpr int NT = BX * BY;
   constexpr int TY = BY * VY;
   constexpr int LX = BX + 2 * R;
   constexpr int LY = TY + 2 * R;
-  constexpr int K = 2 * R + 2;  // queue slots: 2R+1 taps plus one prefetch
+  constexpr int PD = DEEP ? 3 : 1;   // own-column planes in flight
+  constexpr int HS = DEEP ? 2 : 1;   // halo register sets (planes ahead)
+  constexpr int K = 2 * R + 1 + PD;  // even for both choices
   constexpr int NHALO = 2 * R * (TY + BX);
   constexpr int NH = (NHALO + NT - 1) / NT;
   constexpr int NRED = Op::NRED;
+  static_assert(K % 2 == 0, "queue length must be even (LDS and halo parity)");
   __shared__ T lds[2][LY * LX];
 
   Op o = op;
@@ -92,6 +104,7 @@ __global__ void __launch_bounds__(BX* BY) k_stencil(Geom g, StencilW<T> W, int z
   const int tile = lb % ntile, chunk = lb / ntile;
   const int x0 = (tile % tiles_x) * BX, y0 = (tile / tiles_x) * TY;
   const int zbeg = chunk * zc, zend = min(zbeg + zc, g.nz);
+  const int zlast = zend - 1 + R;  // last plane any output of this chunk reads
   const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
   const int gx = x0 + tx, gy0 = y0 + ty * VY;
   const long long colofs = (long long)gy0 * g.px + gx;
@@ -120,22 +133,29 @@ __global__ void __launch_bounds__(BX* BY) k_stencil(Geom g, StencilW<T> W, int z
   }
 
   T q[K][VY];
-  T hreg[NH];
+  T hreg[HS][NH];
   double red[NRED > 0 ? NRED : 1];
 #pragma unroll
   for (int r = 0; r < (NRED > 0 ? NRED : 1); ++r) red[r] = 0.0;
 
-  // planes zbeg-R .. zbeg+R into slots 0..2R, halo of plane zbeg
+  // queue: planes zbeg-R .. zbeg+R+PD-1 into slots 0 .. K-2 (slot of plane z+d at
+  // unrolled step s is (s + R + d) mod K); the last slot is filled by the first prefetch
 #pragma unroll
-  for (int m = 0; m <= 2 * R; ++m) {
-    const long long pb = g.base + (long long)(zbeg - R + m) * g.plane + colofs;
+  for (int m = 0; m < K - 1; ++m) {
+    const int pz = zbeg - R + m;
+    const long long pb = g.base + (long long)pz * g.plane + colofs;
 #pragma unroll
-    for (int v = 0; v < VY; ++v) q[m][v] = o.load(pb + (long long)v * g.px);
+    for (int v = 0; v < VY; ++v) q[m][v] = (pz <= zlast) ? o.load(pb + (long long)v * g.px) : T(0);
   }
-  {
-    const long long hb = g.base + (long long)zbeg * g.plane;
 #pragma unroll
-    for (int m = 0; m < NH; ++m) hreg[m] = hv[m] ? o.load(hb + hg[m]) : T(0);
+  for (int v = 0; v < VY; ++v) q[K - 1][v] = T(0);
+  // halo of planes zbeg .. zbeg+HS-1 into sets 0 .. HS-1
+#pragma unroll
+  for (int h = 0; h < HS; ++h) {
+    const bool ok = zbeg + h < zend;
+    const long long hb = g.base + (long long)(zbeg + h) * g.plane;
+#pragma unroll
+    for (int m = 0; m < NH; ++m) hreg[h][m] = (ok && hv[m]) ? o.load(hb + hg[m]) : T(0);
   }
 
   for (int z0 = zbeg; z0 < zend; z0 += K) {
@@ -144,36 +164,45 @@ __global__ void __launch_bounds__(BX* BY) k_stencil(Geom g, StencilW<T> W, int z
       const int z = z0 + s;
       if (z < zend) {
         T* L = lds[s & 1];
-        // stage plane z: own column from the queue, halo from the prefetch registers
+        const int hs = (HS == 2) ? (s & 1) : 0;
+        // stage plane z: own rows from the queue, halo from its register set
 #pragma unroll
         for (int v = 0; v < VY; ++v) L[(R + ty * VY + v) * LX + R + tx] = q[(s + R) % K][v];
 #pragma unroll
         for (int m = 0; m < NH; ++m)
-          if (hv[m]) L[hl[m]] = hreg[m];
-        // prefetch plane z+R+1 into the slot of plane z-R-1, and the halo of plane z+1
-        if (z + 1 < zend) {
-          const long long pb = g.base + (long long)(z + R + 1) * g.plane + colofs;
+          if (hv[m]) L[hl[m]] = hreg[hs][m];
+        // prefetch: own column of plane z+R+PD, halo of plane z+HS (into the set just staged)
+        if (z + R + PD <= zlast) {
+          const long long pb = g.base + (long long)(z + R + PD) * g.plane + colofs;
 #pragma unroll
-          for (int v = 0; v < VY; ++v) q[(s + 2 * R + 1) % K][v] = o.load(pb + (long long)v * g.px);
-          const long long hb = g.base + (long long)(z + 1) * g.plane;
+          for (int v = 0; v < VY; ++v) q[(s + 2 * R + PD) % K][v] = o.load(pb + (long long)v * g.px);
+        }
+        if (z + HS < zend) {
+          const long long hb = g.base + (long long)(z + HS) * g.plane;
 #pragma unroll
           for (int m = 0; m < NH; ++m)
-            if (hv[m]) hreg[m] = o.load(hb + hg[m]);
+            if (hv[m]) hreg[hs][m] = o.load(hb + hg[m]);
         }
         __syncthreads();
-        // column of the tile around this thread's rows, for the y taps
-        T col[VY + 2 * R];
+        // y taps beyond this thread's rows: R rows above and R below, from LDS
+        T up[R], dn[R];
 #pragma unroll
-        for (int m = 0; m < VY + 2 * R; ++m) col[m] = L[(ty * VY + m) * LX + R + tx];
+        for (int m = 0; m < R; ++m) {
+          up[m] = L[(ty * VY + m) * LX + R + tx];           // row offset m - R from the first own row
+          dn[m] = L[(R + ty * VY + VY + m) * LX + R + tx];  // row offset VY + m
+        }
 #pragma unroll
         for (int v = 0; v < VY; ++v) {
           const T* row = L + (R + ty * VY + v) * LX + R + tx;
           const T c = q[(s + R) % K][v];
           T acc = W.c0 * c;
 #pragma unroll
-          for (int p = 1; p <= R; ++p)
-            acc += W.w[p] * (((q[(s + R - p) % K][v] + q[(s + R + p) % K][v]) + (row[-p] + row[p])) +
-                             (col[v + R - p] + col[v + R + p]));
+          for (int p = 1; p <= R; ++p) {
+            const int a = v - p, b = v + p;  // own-row index of the y neighbours
+            const T ya = (a >= 0) ? q[(s + R) % K][a >= 0 ? a : 0] : up[a + R >= 0 ? a + R : 0];
+            const T yb = (b < VY) ? q[(s + R) % K][b < VY ? b : 0] : dn[b - VY < R ? b - VY : 0];
+            acc += W.w[p] * (((q[(s + R - p) % K][v] + q[(s + R + p) % K][v]) + (row[-p] + row[p])) + (ya + yb));
+          }
           const int gy = gy0 + v;
           if (gx < g.nx && gy < g.ny)
             o.store(g.base + (long long)z * g.plane + (long long)gy * g.px + gx, gx, gy, z, c, acc, red);
@@ -551,147 +580,5 @@ struct GradOp {
     red[G_U2] += u2;
   }
 };
-
-// ----------------------------------------------------------------- nuclei
-__device__ inline double bJ_val(double Z, double s, double rc, double r2) {
-  if (r2 > rc * rc) return 0.0;
-  const double is = 1.0 / s;
-  return -Z * 0.17958712212516656 * is * is * is * exp(-r2 * is * is);  // pi^-3/2
-}
-__device__ inline double VJ_val(double Z, double s, double r) {
-  if (r == 0.0) return -2.0 * Z / (s * 1.7724538509055159);
-  return -Z * erf(r / s) / r;
-}
-
-struct AtomsDev {
-  const double* R;      // 3M
-  const double* Z;      // M
-  const int* cell_start;  // ncell+1
-  const int* cell_atoms;  // M, atom ids sorted by cell
-  int M;
-  int cdim[3];
-  double clo[3];
-  double csize;
-};
-
-// b at every interior node: sum over atoms of the 27 neighbouring cells.
-__global__ void __launch_bounds__(256) k_pseudocharge(Geom g, double h, double ox, double oy, double oz, AtomsDev A,
-                                                       double s, double rc, double* b) {
-  const long long n = (long long)g.nx * g.ny * g.nz;
-  for (long long t = blockIdx.x * 256ll + threadIdx.x; t < n; t += (long long)gridDim.x * 256) {
-    const int i = (int)(t % g.nx);
-    const int j = (int)((t / g.nx) % g.ny);
-    const int k = (int)(t / ((long long)g.nx * g.ny));
-    const double x = ox + i * h, y = oy + j * h, z = oz + k * h;
-    const int ci = (int)floor((x - A.clo[0]) / A.csize);
-    const int cj = (int)floor((y - A.clo[1]) / A.csize);
-    const int ck = (int)floor((z - A.clo[2]) / A.csize);
-    double acc = 0.0;
-    for (int c2 = max(ck - 1, 0); c2 <= min(ck + 1, A.cdim[2] - 1); ++c2)
-      for (int c1 = max(cj - 1, 0); c1 <= min(cj + 1, A.cdim[1] - 1); ++c1)
-        for (int c0 = max(ci - 1, 0); c0 <= min(ci + 1, A.cdim[0] - 1); ++c0) {
-          const int c = (c2 * A.cdim[1] + c1) * A.cdim[0] + c0;
-          for (int a = A.cell_start[c]; a < A.cell_start[c + 1]; ++a) {
-            const int J = A.cell_atoms[a];
-            const double dx = x - A.R[3 * J], dy = y - A.R[3 * J + 1], dz = z - A.R[3 * J + 2];
-            acc += bJ_val(A.Z[J], s, rc, dx * dx + dy * dy + dz * dz);
-          }
-        }
-    b[g.base + (long long)k * g.plane + (long long)j * g.px + i] = acc;
-  }
-}
-
-// Node index box of atom J's ball.
-__device__ inline void ball_box(const Geom& g, double h, const double* o, const double* RJ, double rc, int lo[3],
-                                int hi[3]) {
-  const int n[3] = {g.nx, g.ny, g.nz};
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = max((int)floor((RJ[a] - rc - o[a]) / h) - 1, 0);
-    hi[a] = min((int)ceil((RJ[a] + rc - o[a]) / h) + 1, n[a] - 1);
-  }
-}
-
-// Per atom: self-energy sum_i b_J V_J over the ball (out[J]) and, if phi is
-// given, the force sum_i (grad_h b_J)_i (phi_i - V_J(x_i)) (out3[3J..3J+2]).
-template <int NT>
-__global__ void __launch_bounds__(NT) k_atom_sums(Geom g, double h, double ox, double oy, double oz, AtomsDev A,
-                                                  double s, double rc, StencilW<double> wt, int R,
-                                                  const double* phi, double* out_self, double* out_force) {
-  const int J = blockIdx.x;
-  const double o[3] = {ox, oy, oz};
-  const double RJ[3] = {A.R[3 * J], A.R[3 * J + 1], A.R[3 * J + 2]};
-  const double ZJ = A.Z[J];
-  int lo[3], hi[3];
-  ball_box(g, h, o, RJ, rc, lo, hi);
-  const int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
-  const long long nbox = (long long)ex * ey * ez;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (long long t = threadIdx.x; t < nbox; t += NT) {
-    const int i = lo[0] + (int)(t % ex);
-    const int j = lo[1] + (int)((t / ex) % ey);
-    const int k = lo[2] + (int)(t / ((long long)ex * ey));
-    const double dx = ox + i * h - RJ[0], dy = oy + j * h - RJ[1], dz = oz + k * h - RJ[2];
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 > rc * rc) continue;
-    const double r = sqrt(r2);
-    const double vj = VJ_val(ZJ, s, r);
-    if (out_self) acc[3] += bJ_val(ZJ, s, rc, r2) * vj;
-    if (phi) {
-      double gr[3] = {0.0, 0.0, 0.0};
-      for (int p = 1; p <= R; ++p) {
-        const double ph = p * h;
-        gr[0] += wt.w[p] * (bJ_val(ZJ, s, rc, (dx + ph) * (dx + ph) + dy * dy + dz * dz) -
-                            bJ_val(ZJ, s, rc, (dx - ph) * (dx - ph) + dy * dy + dz * dz));
-        gr[1] += wt.w[p] * (bJ_val(ZJ, s, rc, dx * dx + (dy + ph) * (dy + ph) + dz * dz) -
-                            bJ_val(ZJ, s, rc, dx * dx + (dy - ph) * (dy - ph) + dz * dz));
-        gr[2] += wt.w[p] * (bJ_val(ZJ, s, rc, dx * dx + dy * dy + (dz + ph) * (dz + ph)) -
-                            bJ_val(ZJ, s, rc, dx * dx + dy * dy + (dz - ph) * (dz - ph)));
-      }
-      const double pot = phi[g.base + (long long)k * g.plane + (long long)j * g.px + i] - vj;
-      acc[0] += gr[0] * pot;
-      acc[1] += gr[1] * pot;
-      acc[2] += gr[2] * pot;
-    }
-  }
-  __shared__ double res[4];
-  block_reduce_store<4, NT>(acc, res);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (out_self) out_self[J] = res[3];
-    if (out_force) {
-      out_force[3 * J] = res[0];
-      out_force[3 * J + 1] = res[1];
-      out_force[3 * J + 2] = res[2];
-    }
-  }
-}
-
-// ----------------------------------------------------------------- layout conversion
-template <typename TS, typename TD>
-__global__ void __launch_bounds__(256) k_pack(Geom g, const TS* dense, TD* padded, int absval) {
-  const long long n = (long long)g.nx * g.ny * g.nz;
-  for (long long t = blockIdx.x * 256ll + threadIdx.x; t < n; t += (long long)gridDim.x * 256) {
-    const long long i = t % g.nx, j = (t / g.nx) % g.ny, k = t / ((long long)g.nx * g.ny);
-    TS v = dense[t];
-    if (absval) v = v < TS(0) ? -v : v;
-    padded[g.base + k * g.plane + j * g.px + i] = (TD)v;
-  }
-}
-template <typename TS, typename TD>
-__global__ void __launch_bounds__(256) k_unpack(Geom g, const TS* padded, TD* dense, int absval) {
-  const long long n = (long long)g.nx * g.ny * g.nz;
-  for (long long t = blockIdx.x * 256ll + threadIdx.x; t < n; t += (long long)gridDim.x * 256) {
-    const long long i = t % g.nx, j = (t / g.nx) % g.ny, k = t / ((long long)g.nx * g.ny);
-    TS v = padded[g.base + k * g.plane + j * g.px + i];
-    if (absval) v = v < TS(0) ? -v : v;
-    dense[t] = (TD)v;
-  }
-}
-
-// Fill of a padded array (halo included) with a value.
-template <typename T>
-__global__ void __launch_bounds__(256) k_fill(T* a, long long n, T val) {
-  for (long long t = blockIdx.x * 256ll + threadIdx.x; t < n; t += (long long)gridDim.x * 256) a[t] = val;
-}
 
 }  // namespace alofdft
