@@ -34,8 +34,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     ap.add_argument("--sample-every", type=int, default=8, help="CG kernel launches per timed sample")
-    ap.add_argument("--mode", default="solve", choices=["solve", "stencil"],
-                    help="stencil: only the streaming stencil measurement (for counter profiling)")
+    ap.add_argument("--mode", default="solve", choices=["solve", "stencil", "serve"],
+                    help="stencil: only the streaming stencil measurement (for counter profiling); "
+                         "serve: the request stream of fcc 1-3 clusters through the serving loop")
+    ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
+    ap.add_argument("--rate-factor", type=float, default=1.0,
+                    help="serve: arrival rate as a multiple of the sequential FP64 service rate")
+    ap.add_argument("--slots", type=int, default=4, help="serve: concurrent request slots")
     return ap.parse_args()
 
 
@@ -82,6 +87,114 @@ def cpu_baseline(system, seconds):
                       f"residual in {dt:.1f} s (stencil point updates per second of the same operator)"}
 
 
+def fifo_latencies(arrivals, service):
+    """Single-server FIFO queue: latency (finish - arrival) of each request."""
+    t, out = 0.0, []
+    for a, s in zip(arrivals, service):
+        t = max(t, a) + s
+        out.append(t - a)
+    return out
+
+
+def pct(v, q):
+    import math
+
+    v = sorted(v)
+    k = max(1, math.ceil(q * len(v)))
+    return v[min(len(v), k) - 1]
+
+
+def serve(args):
+    """Request stream: fcc m^3 clusters, m ~ U{1,2,3} (seed 2014), displacement seed 10000+k,
+    Poisson arrivals (seed 2015) at rate_factor x the sequential FP64 service rate; served
+    with FP32+FP64-refined solves through the serving loop, against a FIFO replay of the
+    same arrivals with the measured sequential FP64 service times."""
+    import threading
+
+    import numpy as np
+
+    import paper_1405_6456_amd as lib
+    from paper_1405_6456_amd import synth
+
+    reqs = synth.serving_requests(args.requests)
+    ms = [S.M // 4 for S in reqs]
+    ms = [round(m ** (1 / 3)) for m in ms]
+    ctx = lib.Context(0)
+    # sequential FP64 service time per cluster size (first request of each size), after a warm-up
+    ctx.solve(reqs[0], lib.default_params(), None, want_fields=False)
+    svc64, first = {}, {}
+    for k, m in enumerate(ms):
+        if m not in first:
+            first[m] = k
+    for m, k in sorted(first.items()):
+        t = time.perf_counter()
+        ctx.solve(reqs[k], lib.default_params(), None, want_fields=False)
+        svc64[m] = time.perf_counter() - t
+    service = [svc64[m] for m in ms]
+    c_seq = 1.0 / (sum(service) / len(service))
+    rate = args.rate_factor * c_seq
+    arrivals = synth.arrival_times(len(reqs), rate)
+    seq_lat = fifo_latencies(list(arrivals), service)
+
+    srv = lib.Server(0, max_slots=args.slots)
+    prm = lib.default_params(precision=lib.FP32_REFINED)
+    tickets = [None] * len(reqs)
+    t0 = time.perf_counter()
+
+    def submitter():
+        for k, S in enumerate(reqs):
+            d = arrivals[k] - (time.perf_counter() - t0)
+            if d > 0:
+                time.sleep(d)
+            tickets[k] = srv.submit(S, prm)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    results = [None] * len(reqs)
+    pending = set(range(len(reqs)))
+    while pending:
+        for k in list(pending):
+            if tickets[k] is not None:
+                r = srv.poll(tickets[k])
+                if r is not None:
+                    results[k] = r
+                    pending.discard(k)
+        time.sleep(0.005)
+    th.join()
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    # accuracy of served results against the FP64 path, one request per size
+    err_e, err_f = 0.0, 0.0
+    for m, k in sorted(first.items()):
+        ref = ctx.solve(reqs[k], lib.default_params(), None, want_fields=False)
+        err_e = max(err_e, abs(results[k]["E_total"] - ref["E_total"]) / reqs[k].M)
+        err_f = max(err_f, float(np.abs(results[k]["forces"] - ref["forces"]).max()))
+    ctx.close()
+    line = {
+        "metric": "Gpts/s stencil (%HBM peak); AL-OFDFT solves/s, p50/p99 latency vs FP64",
+        "value": round(st["solves_per_s"], 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f32 stencil/CG + f64 refinement",
+        "data": "synthetic",
+        "config": {"workload": f"serving stream: {len(reqs)} fcc m^3 clusters, m in {{1,2,3}} "
+                               f"(48^3..79^3 nodes), Poisson arrivals at {args.rate_factor} x sequential "
+                               f"FP64 rate", "slots": args.slots},
+        "served": {"p50_ms": round(st["p50_ms"], 1), "p99_ms": round(st["p99_ms"], 1),
+                   "mean_ms": round(st["mean_ms"], 1), "solves_per_s": round(st["solves_per_s"], 4),
+                   "wall_s": round(wall, 1), "completed": st["completed"],
+                   "statuses": sorted(set(r["status"] for r in results))},
+        "sequential_fp64": {"p50_ms": round(1e3 * pct(seq_lat, 0.5), 1), "p99_ms": round(1e3 * pct(seq_lat, 0.99), 1),
+                            "service_s": {str(m): round(v, 3) for m, v in svc64.items()},
+                            "solves_per_s": round(c_seq, 4)},
+        "arrival_rate_per_s": round(rate, 4),
+        "err_vs_fp64": {"E_per_atom": err_e, "F_max": err_f},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -95,6 +208,8 @@ def main():
     from paper_1405_6456_amd import synth
 
     torch.cuda.set_device(0)
+    if args.mode == "serve":
+        return serve(args)
     S = synth.config(args.workload)
     if args.mode == "stencil":
         ctx = lib.Context(0)

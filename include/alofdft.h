@@ -209,13 +209,14 @@ int alofdft_forces(alofdft_ctx* ctx, const alofdft_system* sys, const alofdft_pa
 int alofdft_bench_stencil(alofdft_ctx* ctx, const int n[3], int fd_half_width, int dtype, int reps, int nbuf,
                           double* ms_per_apply);
 
-/* Launch tuning of a context: stencil tile variant for the order-12 stencil (0: 64x8
+/* Launch tuning of a context: stencil tile variant for the order-12 stencil (-1:
+ * chosen per grid -- 64x4 with the deep prefetch for small grids, else variant 0; 0: 64x8
  * nodes in x-y, two rows per thread, z column prefetched one plane ahead; 1: 64x4,
  * one row per thread, three planes ahead; 2: 64x8, one row, one ahead; 3: 64x8, one
  * row, three ahead; 4: 64x4, one row, one ahead), the target number of stencil
  * workgroups (sets how many z chunks each XCD gets), and the FP32 inner-solve
  * residual reduction 10^-inner_tol_exp of the refined Poisson solve (1..7).
- * Defaults 0, 1024, 4.  INVALID_ARGUMENT outside those ranges. */
+ * Defaults -1, 1024, 4.  INVALID_ARGUMENT outside those ranges. */
 int alofdft_set_tuning(alofdft_ctx* ctx, int stencil_variant, int target_blocks, int inner_tol_exp);
 
 /* Measurement of the dominant kernel.  With sample_every > 0, every
@@ -230,6 +231,51 @@ int alofdft_profile_cg_kernel(alofdft_ctx* ctx, int sample_every);
  * the refined solve): number of timed launches, mean duration in ms, and the grid
  * points (n[0]*n[1]*n[2]) of the last timed launch.  All three pointers required. */
 int alofdft_cg_kernel_stats(alofdft_ctx* ctx, int dtype, long long* launches, double* mean_ms, long long* points);
+
+/* ------------------------------------------------------------------ serving
+ * A request loop that solves independent ground-state requests (systems of any
+ * grid size) concurrently on one GPU: up to max_slots requests are on the device
+ * at once, each on its own HIP stream with its own resident work arrays, so their
+ * kernels overlap; a queued request is admitted as soon as a slot is free and the
+ * HBM footprint of the admitted requests stays within hbm_budget_bytes (continuous
+ * batching).  A request's result does not depend on what else is running (every
+ * reduction has a fixed order per request).  submit and poll are thread safe. */
+typedef struct alofdft_server alofdft_server;
+
+typedef struct {
+  long long submitted, admitted, completed, rejected;
+  int queued, running;
+  double p50_ms, p99_ms, mean_ms; /* submit-to-finish latency of completed requests */
+  double solves_per_s;            /* completed / (last finish - first submit) */
+  double hbm_reserved_bytes;      /* footprint currently reserved by running requests */
+} alofdft_server_stats;
+
+/* Device memory (bytes) one request of this system reserves while it runs: the
+ * padded work arrays of the solve in both precisions plus the dense I/O arrays.
+ * Returns 0 for an invalid system. */
+size_t alofdft_footprint_bytes(const alofdft_system* sys, const alofdft_params* prm);
+
+/* Starts max_slots (1..16) worker slots on HIP device `hip_device`.  OUT_OF_MEMORY
+ * or DEVICE_ERROR if the streams cannot be created. */
+int alofdft_server_create(alofdft_server** out, int hip_device, size_t hbm_budget_bytes, int max_slots);
+
+/* Queues a request; the system (atoms copied) and params are copied before return.
+ * *ticket identifies it.  REJECTED if its footprint exceeds the whole budget;
+ * INVALID_ARGUMENT for an invalid system (same checks as alofdft_solve). */
+int alofdft_server_submit(alofdft_server* srv, const alofdft_system* sys, const alofdft_params* prm,
+                          uint64_t* ticket);
+
+/* PENDING while the request is queued or running; otherwise its final status with
+ * *res filled (and, when not NULL, u_out: host grid array, forces_out: host 3*M).
+ * A finished request is released by the first poll that returns its status;
+ * INVALID_ARGUMENT for an unknown ticket. */
+int alofdft_server_poll(alofdft_server* srv, uint64_t ticket, alofdft_result* res, double* u_out,
+                        double* forces_out);
+
+int alofdft_server_get_stats(alofdft_server* srv, alofdft_server_stats* st);
+
+/* Waits for running and queued requests to finish, then stops the workers. */
+void alofdft_server_destroy(alofdft_server* srv);
 
 #ifdef __cplusplus
 }

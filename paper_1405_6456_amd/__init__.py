@@ -56,6 +56,12 @@ class Energy(C.Structure):
                                            "C_h", "L", "grad_norm")] + [("cg_iters", C.c_longlong)]
 
 
+class ServerStats(C.Structure):
+    _fields_ = [(k, C.c_longlong) for k in ("submitted", "admitted", "completed", "rejected")] + \
+               [("queued", C.c_int), ("running", C.c_int)] + \
+               [(k, C.c_double) for k in ("p50_ms", "p99_ms", "mean_ms", "solves_per_s", "hbm_reserved_bytes")]
+
+
 class AlofdftError(RuntimeError):
     def __init__(self, status, detail=""):
         super().__init__(f"alofdft status {status}: {detail}")
@@ -95,6 +101,14 @@ def lib():
         L.alofdft_pseudocharge.argtypes = [_VP, C.POINTER(SystemS), C.POINTER(Params), _VP, _DP]
         L.alofdft_forces.argtypes = [_VP, C.POINTER(SystemS), C.POINTER(Params), _VP, _DP]
         L.alofdft_bench_stencil.argtypes = [_VP, C.POINTER(C.c_int), C.c_int, C.c_int, C.c_int, C.c_int, _DP]
+        L.alofdft_footprint_bytes.restype = C.c_size_t
+        L.alofdft_footprint_bytes.argtypes = [C.POINTER(SystemS), C.POINTER(Params)]
+        L.alofdft_server_create.argtypes = [C.POINTER(_VP), C.c_int, C.c_size_t, C.c_int]
+        L.alofdft_server_submit.argtypes = [_VP, C.POINTER(SystemS), C.POINTER(Params), C.POINTER(C.c_uint64)]
+        L.alofdft_server_poll.argtypes = [_VP, C.c_uint64, C.POINTER(Result), _DP, _DP]
+        L.alofdft_server_get_stats.argtypes = [_VP, C.POINTER(ServerStats)]
+        L.alofdft_server_destroy.argtypes = [_VP]
+        L.alofdft_server_destroy.restype = None
         L.alofdft_profile_cg_kernel.argtypes = [_VP, C.c_int]
         L.alofdft_cg_kernel_stats.argtypes = [_VP, C.c_int, C.POINTER(C.c_longlong), _DP, C.POINTER(C.c_longlong)]
         _lib = L
@@ -169,7 +183,7 @@ class Context:
         except Exception:
             pass
 
-    def set_tuning(self, variant=0, target_blocks=1024, inner_tol_exp=4):
+    def set_tuning(self, variant=-1, target_blocks=1024, inner_tol_exp=4):
         _check(self, lib().alofdft_set_tuning(self.handle, variant, target_blocks, inner_tol_exp))
 
     # ------------------------------------------------------------- full solve
@@ -291,3 +305,79 @@ def result_dict(res: Result) -> dict:
     out = {k: getattr(res, k) for k, _ in Result._fields_ if k != "counts"}
     out.update({k: getattr(res.counts, k) for k, _ in Counts._fields_})
     return out
+
+
+def footprint_bytes(system, params=None) -> int:
+    """Device bytes one request of this system reserves while it is solved."""
+    S = SystemArgs(system)
+    return int(lib().alofdft_footprint_bytes(C.byref(S.s), C.byref(params or default_params())))
+
+
+class Server:
+    """Continuous-batching request loop on one GPU (see alofdft_server_* in the C ABI)."""
+
+    def __init__(self, device=0, hbm_budget_bytes=None, max_slots=4):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the alofdft server runs only on the GPU")
+        if hbm_budget_bytes is None:
+            free, _ = torch.cuda.mem_get_info(device)
+            hbm_budget_bytes = int(0.9 * free)
+        h = C.c_void_p()
+        st = lib().alofdft_server_create(C.byref(h), int(device), int(hbm_budget_bytes), int(max_slots))
+        if st != OK:
+            raise AlofdftError(st, lib().alofdft_strerror(st).decode())
+        self.handle = h
+        self._shapes = {}
+
+    def submit(self, system, params=None):
+        """Queue a solve; returns a ticket.  Raises AlofdftError(REJECTED) if it can never fit."""
+        S = SystemArgs(system)
+        t = C.c_uint64()
+        st = lib().alofdft_server_submit(self.handle, C.byref(S.s), C.byref(params or default_params()),
+                                         C.byref(t))
+        if st != OK:
+            raise AlofdftError(st, lib().alofdft_strerror(st).decode())
+        self._shapes[t.value] = (system.grid.shape, S.s.M)
+        return t.value
+
+    def poll(self, ticket):
+        """None while pending; else a result dict with u and forces (the ticket is released)."""
+        shape, M = self._shapes[ticket]
+        res = Result()
+        u = np.zeros(shape)
+        f = np.zeros((M, 3))
+        st = lib().alofdft_server_poll(self.handle, ticket, C.byref(res), u.ctypes.data_as(_DP),
+                                       f.ctypes.data_as(_DP))
+        if st == PENDING:
+            return None
+        del self._shapes[ticket]
+        out = result_dict(res)
+        out.update(status=st, u=u, forces=f)
+        return out
+
+    def wait(self, ticket, poll_s=0.002):
+        import time
+
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            time.sleep(poll_s)
+
+    def stats(self):
+        s = ServerStats()
+        lib().alofdft_server_get_stats(self.handle, C.byref(s))
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().alofdft_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

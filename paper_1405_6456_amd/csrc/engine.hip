@@ -13,8 +13,13 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <condition_variable>
+#include <deque>
 #include <functional>
 #include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -33,7 +38,7 @@ struct alofdft_ctx {
   std::map<std::string, std::pair<void*, size_t>> bufs;
   double* pin = nullptr;  // pinned host scalars
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  int variant = 0;        // stencil tile variant
+  int variant = -1;       // stencil tile variant (-1: chosen per grid)
   int target_blocks = 1024;
   int inner_tol_exp = 4;  // FP32 inner CG reduces the residual by 10^-inner_tol_exp
   // geometry each padded work array was last zeroed for (its halo is zero only then)
@@ -1057,6 +1062,131 @@ int solve_impl(alofdft_ctx* c, const alofdft_system* sys, const alofdft_params* 
   return st;
 }
 
+// ----------------------------------------------------------------- serving
+size_t footprint(const alofdft_system* s, const alofdft_params* p) {
+  const Geom g = make_geom(s->n, p->fd_half_width);
+  const size_t T = (size_t)g.total;
+  const size_t n = (size_t)s->n[0] * s->n[1] * s->n[2];
+  // solver arrays (12), FP64 CG (4), refinement residual (1): double; FP32 CG (4) + correction (1): float
+  const size_t arrays = (12 + 4 + 1) * 8 * T + (4 + 1) * 4 * T;
+  const size_t dense = 3 * 8 * n;  // initial guess, u and phi outputs
+  // block partials, scalars, atom arrays and the cell list (with slack)
+  const size_t small = (size_t)(max_stencil_blocks(g, 4096) + 4 * kPointwiseBlocks) * 16 * 8 + 128 * (size_t)s->M +
+                       (size_t)(1 << 20);
+  return arrays + dense + small;
+}
+
+size_t held_bytes(const alofdft_ctx* c) {
+  size_t b = 0;
+  for (auto& kv : c->bufs) b += kv.second.second;
+  return b;
+}
+
+void free_all(alofdft_ctx* c) {
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& kv : c->bufs) (void)hipFree(kv.second.first);
+  c->bufs.clear();
+  c->geom_key.clear();
+}
+
+struct Request {
+  uint64_t id = 0;
+  alofdft_system sys{};
+  std::vector<double> R, Z;
+  alofdft_params prm{};
+  size_t fp = 0;
+  std::chrono::steady_clock::time_point t_submit, t_start, t_end;
+  int status = ALOFDFT_PENDING;
+  alofdft_result res{};
+  std::vector<double> u, forces;
+};
+
+}  // namespace
+
+struct alofdft_server {
+  int device = 0;
+  size_t budget = 0;
+  std::vector<alofdft_ctx*> ctx;
+  std::vector<hipStream_t> streams;
+  std::vector<size_t> held;  // bytes each slot's context holds
+  std::vector<std::thread> workers;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<std::shared_ptr<Request>> queue;
+  std::map<uint64_t, std::shared_ptr<Request>> reqs;
+  size_t reserved = 0;  // footprints of running requests beyond what their slots already hold
+  int running = 0;
+  bool stop = false;
+  uint64_t next_id = 1;
+  long long submitted = 0, admitted = 0, completed = 0, rejected = 0;
+  std::vector<double> lat_ms;
+  bool have_first = false;
+  std::chrono::steady_clock::time_point first_submit, last_end;
+};
+
+namespace {
+
+// Bytes in use on the device if slot w takes a request of footprint fp.
+size_t demand(const alofdft_server* s, int w, size_t fp) {
+  size_t tot = s->reserved;
+  for (size_t i = 0; i < s->held.size(); ++i) tot += (int)i == w ? std::max(s->held[i], fp) : s->held[i];
+  return tot;
+}
+
+void worker_loop(alofdft_server* s, int w) {
+  alofdft_ctx* c = s->ctx[w];
+  (void)hipSetDevice(s->device);
+  for (;;) {
+    std::shared_ptr<Request> r;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      for (;;) {
+        if (s->stop && s->queue.empty()) return;
+        if (!s->queue.empty()) {
+          const size_t fp = s->queue.front()->fp;
+          if (demand(s, w, fp) <= s->budget) break;
+          if (s->held[w] > fp) {  // this idle slot's cached arrays are in the way: drop them
+            free_all(c);
+            s->held[w] = 0;
+            if (demand(s, w, fp) <= s->budget) break;
+          }
+        }
+        s->cv.wait(lk);
+      }
+      r = s->queue.front();
+      s->queue.pop_front();
+      s->reserved += r->fp > s->held[w] ? r->fp - s->held[w] : 0;
+      s->running++;
+      s->admitted++;
+    }
+    r->t_start = std::chrono::steady_clock::now();
+    const long long n = npoints(r->sys.n);
+    r->u.assign((size_t)n, 0.0);
+    r->forces.assign(3 * (size_t)r->sys.M, 0.0);
+    int st = guarded(c, [&]() {
+      double* du = bufT<double>(c, "io.uout", (size_t)n);
+      int rc = solve_impl(c, &r->sys, &r->prm, nullptr, nullptr, du, nullptr, r->forces.data(), &r->res);
+      HIPC(c, hipMemcpyAsync(r->u.data(), du, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+      sync(c);
+      return rc;
+    });
+    r->t_end = std::chrono::steady_clock::now();
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      const size_t before = s->held[w];
+      s->held[w] = held_bytes(c);
+      s->reserved -= r->fp > before ? r->fp - before : 0;
+      s->running--;
+      s->completed++;
+      r->status = st;
+      r->res.status = st;
+      s->lat_ms.push_back(std::chrono::duration<double, std::milli>(r->t_end - r->t_submit).count());
+      s->last_end = r->t_end;
+    }
+    s->cv.notify_all();
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -1145,7 +1275,7 @@ void alofdft_destroy(alofdft_ctx* c) {
 }
 
 int alofdft_set_tuning(alofdft_ctx* c, int stencil_variant, int target_blocks, int inner_tol_exp) {
-  if (!c || stencil_variant < 0 || stencil_variant > 4 || target_blocks < 1 || inner_tol_exp < 1 || inner_tol_exp > 7)
+  if (!c || stencil_variant < -1 || stencil_variant > 4 || target_blocks < 1 || inner_tol_exp < 1 || inner_tol_exp > 7)
     return ALOFDFT_INVALID_ARGUMENT;
   c->variant = stencil_variant;
   c->target_blocks = target_blocks;
@@ -1355,6 +1485,144 @@ int alofdft_bench_stencil(alofdft_ctx* c, const int n[3], int fdn, int dtype, in
     *ms = (double)t / reps;
     return ALOFDFT_OK;
   });
+}
+
+size_t alofdft_footprint_bytes(const alofdft_system* sys, const alofdft_params* prm) {
+  if (!sys || !prm || prm->fd_half_width < 1 || prm->fd_half_width > kMaxRadius) return 0;
+  for (int a = 0; a < 3; ++a)
+    if (sys->n[a] < 1) return 0;
+  return footprint(sys, prm);
+}
+
+int alofdft_server_create(alofdft_server** out, int hip_device, size_t hbm_budget_bytes, int max_slots) {
+  if (!out || max_slots < 1 || max_slots > 16 || hbm_budget_bytes == 0) return ALOFDFT_INVALID_ARGUMENT;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) return ALOFDFT_DEVICE_ERROR;
+  if (hipSetDevice(hip_device) != hipSuccess) return ALOFDFT_DEVICE_ERROR;
+  alofdft_server* s = new (std::nothrow) alofdft_server();
+  if (!s) return ALOFDFT_OUT_OF_MEMORY;
+  s->device = hip_device;
+  s->budget = hbm_budget_bytes;
+  for (int w = 0; w < max_slots; ++w) {
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      alofdft_server_destroy(s);
+      return ALOFDFT_DEVICE_ERROR;
+    }
+    s->streams.push_back(st);
+    alofdft_ctx* c = nullptr;
+    const int rc = alofdft_create(&c, hip_device, st);
+    if (rc != ALOFDFT_OK) {
+      alofdft_server_destroy(s);
+      return rc;
+    }
+    s->ctx.push_back(c);
+    s->held.push_back(0);
+  }
+  for (int w = 0; w < max_slots; ++w) s->workers.emplace_back(worker_loop, s, w);
+  *out = s;
+  return ALOFDFT_OK;
+}
+
+int alofdft_server_submit(alofdft_server* s, const alofdft_system* sys, const alofdft_params* prm, uint64_t* ticket) {
+  if (!s || !sys || !prm || !ticket) return ALOFDFT_INVALID_ARGUMENT;
+  auto r = std::make_shared<Request>();
+  {
+    alofdft_ctx tmp;  // validation only (no device work)
+    try {
+      validate(&tmp, sys, prm);
+    } catch (const Fail& f) {
+      return f.code;
+    }
+  }
+  r->R.assign(sys->R, sys->R + 3 * (size_t)sys->M);
+  r->Z.assign(sys->Z, sys->Z + (size_t)sys->M);
+  r->sys = *sys;
+  r->sys.R = r->R.data();
+  r->sys.Z = r->Z.data();
+  r->prm = *prm;
+  r->fp = footprint(sys, prm);
+  r->t_submit = std::chrono::steady_clock::now();
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->submitted++;
+  if (!s->have_first) {
+    s->first_submit = r->t_submit;
+    s->have_first = true;
+  }
+  if (r->fp > s->budget) {
+    s->rejected++;
+    return ALOFDFT_REJECTED;
+  }
+  r->id = s->next_id++;
+  *ticket = r->id;
+  s->reqs[r->id] = r;
+  s->queue.push_back(r);
+  s->cv.notify_all();
+  return ALOFDFT_OK;
+}
+
+int alofdft_server_poll(alofdft_server* s, uint64_t ticket, alofdft_result* res, double* u_out, double* forces_out) {
+  if (!s) return ALOFDFT_INVALID_ARGUMENT;
+  std::shared_ptr<Request> r;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return ALOFDFT_INVALID_ARGUMENT;
+    if (it->second->status == ALOFDFT_PENDING) return ALOFDFT_PENDING;
+    r = it->second;
+    s->reqs.erase(it);
+  }
+  if (res) *res = r->res;
+  if (u_out) std::memcpy(u_out, r->u.data(), sizeof(double) * r->u.size());
+  if (forces_out) std::memcpy(forces_out, r->forces.data(), sizeof(double) * r->forces.size());
+  return r->status;
+}
+
+int alofdft_server_get_stats(alofdft_server* s, alofdft_server_stats* st) {
+  if (!s || !st) return ALOFDFT_INVALID_ARGUMENT;
+  std::lock_guard<std::mutex> lk(s->mu);
+  std::memset(st, 0, sizeof(*st));
+  st->submitted = s->submitted;
+  st->admitted = s->admitted;
+  st->completed = s->completed;
+  st->rejected = s->rejected;
+  st->queued = (int)s->queue.size();
+  st->running = s->running;
+  size_t hb = s->reserved;
+  for (size_t h : s->held) hb += h;
+  st->hbm_reserved_bytes = (double)hb;
+  if (!s->lat_ms.empty()) {
+    std::vector<double> v = s->lat_ms;
+    std::sort(v.begin(), v.end());
+    auto rank = [&](double q) {  // nearest-rank percentile
+      size_t k = (size_t)std::ceil(q * v.size());
+      return v[std::min(v.size() - 1, k > 0 ? k - 1 : 0)];
+    };
+    st->p50_ms = rank(0.50);
+    st->p99_ms = rank(0.99);
+    double sum = 0.0;
+    for (double x : v) sum += x;
+    st->mean_ms = sum / v.size();
+    const double span = std::chrono::duration<double>(s->last_end - s->first_submit).count();
+    st->solves_per_s = span > 0 ? s->completed / span : 0.0;
+  }
+  return ALOFDFT_OK;
+}
+
+void alofdft_server_destroy(alofdft_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv.notify_all();
+  for (auto& t : s->workers)
+    if (t.joinable()) t.join();
+  for (alofdft_ctx* c : s->ctx) alofdft_destroy(c);
+  (void)hipSetDevice(s->device);
+  for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+  delete s;
 }
 
 }  // extern "C"

@@ -1,0 +1,110 @@
+"""Serving: concurrent requests of different grid sizes give the same results as
+solving each alone, admission follows the HBM budget, and the served results match
+the FP64 path."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1405_6456_amd import synth
+from tests.gpu_util import ctx
+
+pytestmark = pytest.mark.gpu
+
+
+def requests():
+    # four small systems of different grid sizes (21^3 .. 48^3)
+    out = []
+    for L, n, shift in ((16.0, 21, (0.11, -0.07, 0.05)), (17.6, 23, (-0.2, 0.1, 0.0)), (18.0, 25, (0.0, 0.0, 0.3))):
+        S = synth.single_atom(L=L, n=n)
+        S.R[0] += np.array(shift)
+        out.append(S)
+    out.append(synth.fcc_cluster(1, seed=10001, name="fcc1"))
+    return out
+
+
+@pytest.fixture(scope="module")
+def alone():
+    import paper_1405_6456_amd as lib
+
+    c = ctx()
+    prm = lib.default_params(precision=lib.FP32_REFINED)
+    res = [c.solve(S, prm, None) for S in requests()]
+    c.close()
+    return res
+
+
+def test_same_alone_and_in_the_mix(alone):
+    import paper_1405_6456_amd as lib
+
+    ctx().close()  # skips without a GPU
+    srv = lib.Server(0, max_slots=4)
+    prm = lib.default_params(precision=lib.FP32_REFINED)
+    reqs = requests()
+    # submit twice in interleaved order so different sizes overlap on the device
+    tickets = [(i, srv.submit(S, prm)) for _ in range(2) for i, S in enumerate(reqs)]
+    for i, t in tickets:
+        r = srv.wait(t)
+        a = alone[i]
+        assert r["status"] == 0 and a["status"] == 0
+        assert abs(r["E_total"] - a["E_total"]) <= 1e-10 * max(1.0, abs(a["E_total"]))
+        assert np.abs(r["forces"] - a["forces"]).max() <= 1e-10
+        assert np.abs(r["u"] - a["u"]).max() <= 1e-10 * np.abs(a["u"]).max()
+    st = srv.stats()
+    assert st["completed"] == len(tickets) and st["rejected"] == 0 and st["queued"] == 0
+    assert st["p50_ms"] > 0 and st["p99_ms"] >= st["p50_ms"] and st["solves_per_s"] > 0
+    srv.close()
+
+
+def test_served_matches_fp64_path(alone):
+    import paper_1405_6456_amd as lib
+
+    c = ctx()
+    for S, a in zip(requests(), alone):
+        ref = c.solve(S, lib.default_params(precision=lib.FP64), None)
+        assert abs(a["E_total"] - ref["E_total"]) / S.M <= 1e-5
+        assert np.abs(a["forces"] - ref["forces"]).max() <= 1e-4
+    c.close()
+
+
+def test_admission_by_footprint():
+    import paper_1405_6456_amd as lib
+
+    ctx().close()
+    reqs = requests()
+    prm = lib.default_params(precision=lib.FP32_REFINED)
+    fps = [lib.footprint_bytes(S, prm) for S in reqs]
+    # a budget below the largest request rejects it; the rest still run, one at a time
+    budget = max(fps) - 1
+    srv = lib.Server(0, hbm_budget_bytes=budget, max_slots=4)
+    with pytest.raises(lib.AlofdftError) as err:
+        srv.submit(reqs[fps.index(max(fps))], prm)
+    assert err.value.status == lib.REJECTED
+    small = [S for S, f in zip(reqs, fps) if f <= budget]
+    tickets = [srv.submit(S, prm) for S in small]
+    peak = 0
+    while True:
+        st = srv.stats()
+        peak = max(peak, st["hbm_reserved_bytes"])
+        if st["completed"] == len(tickets):
+            break
+        time.sleep(0.002)
+    assert peak <= budget
+    for t in tickets:
+        assert srv.wait(t)["status"] == 0
+    st = srv.stats()
+    assert st["rejected"] == 1 and st["completed"] == len(tickets)
+    srv.close()
+
+
+def test_invalid_requests_are_refused():
+    import paper_1405_6456_amd as lib
+
+    ctx().close()
+    srv = lib.Server(0, max_slots=1)
+    S = synth.single_atom(L=16.0, n=21)
+    S.R[0] = [1.0, 8.0, 8.0]  # ball of radius 7 leaves the box
+    with pytest.raises(lib.AlofdftError) as err:
+        srv.submit(S, lib.default_params())
+    assert err.value.status == lib.INVALID_ARGUMENT
+    srv.close()
