@@ -209,14 +209,28 @@ int alofdft_forces(alofdft_ctx* ctx, const alofdft_system* sys, const alofdft_pa
 int alofdft_bench_stencil(alofdft_ctx* ctx, const int n[3], int fd_half_width, int dtype, int reps, int nbuf,
                           double* ms_per_apply);
 
-/* Launch tuning of a context: stencil tile variant for the order-12 stencil (-1:
- * chosen per grid -- 64x4 with the deep prefetch for small grids, else variant 0; 0: 64x8
- * nodes in x-y, two rows per thread, z column prefetched one plane ahead; 1: 64x4,
- * one row per thread, three planes ahead; 2: 64x8, one row, one ahead; 3: 64x8, one
- * row, three ahead; 4: 64x4, one row, one ahead), the target number of stencil
- * workgroups (sets how many z chunks each XCD gets), and the FP32 inner-solve
- * residual reduction 10^-inner_tol_exp of the refined Poisson solve (1..7).
- * Defaults -1, 1024, 4.  INVALID_ARGUMENT outside those ranges. */
+/* Launch tuning of a context.  stencil_variant selects the schedule of the
+ * stencil passes (the residual pass of the energy gradient always uses the
+ * register-addressed 64x4 kernel):
+ *   -1  automatic: buffer-addressed streaming kernel over 64x8 tiles (two rows per
+ *       thread, z column one plane ahead); the plain FP64 Laplacian of grids with
+ *       at least 150^3 nodes uses the forward-accumulating kernel over 64x16 tiles,
+ *       two planes ahead; radii other than 6 always use the first.
+ *   0..4  register-addressed kernels (order 12): 0: 64x8 nodes, two rows per
+ *       thread, one plane ahead; 1: 64x4, one row, three ahead; 2: 64x8, one row,
+ *       one ahead; 3: 64x8, one row, three ahead; 4: 64x4, one row, one ahead.
+ *   5..10  buffer-addressed streaming kernel (order 12), (waves, rows per thread,
+ *       planes ahead): 5 (4,2,1), 6 (4,4,1), 7 (4,2,3), 8 (4,4,3), 9 (8,2,1),
+ *       10 (2,8,1).
+ *   11..16  forward-accumulating kernel (order 12): 11 (4,2,1), 12 (4,4,1),
+ *       13 (4,2,2), 14 (8,2,1), 15 (4,4,2), 16 (8,4,1).
+ *   100 + v  variant v with every z chunk swept upwards (v in 5..16; by default
+ *       odd chunks are swept downwards).
+ * target_blocks is the number of stencil workgroups to aim for (it sets the z
+ * chunk length); 0 fills one round of the workgroups the device holds at once.
+ * inner_tol_exp is the FP32 inner-solve residual reduction 10^-inner_tol_exp of
+ * the refined Poisson solve (1..7).  Defaults -1, 0, 4.  INVALID_ARGUMENT outside
+ * those ranges.  Every variant computes the same stencil; they differ in speed. */
 int alofdft_set_tuning(alofdft_ctx* ctx, int stencil_variant, int target_blocks, int inner_tol_exp);
 
 /* Measurement of the dominant kernel.  With sample_every > 0, every

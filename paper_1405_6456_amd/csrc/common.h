@@ -9,7 +9,7 @@ namespace alofdft {
 
 constexpr int kMaxRadius = 8;       // fd half width n <= 8
 constexpr int kPointwiseThreads = 256;
-constexpr int kPointwiseBlocks = 1024;  // grid-stride blocks of the pointwise kernels
+constexpr int kPointwiseBlocks = 2048;  // grid-stride blocks of the pointwise kernels
 constexpr int kMaxRed = 12;         // reductions per kernel
 
 // Padded storage of one grid array: the interior n = (nx, ny, nz) is surrounded

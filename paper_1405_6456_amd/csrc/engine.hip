@@ -39,7 +39,7 @@ struct alofdft_ctx {
   double* pin = nullptr;  // pinned host scalars
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int variant = -1;       // stencil tile variant (-1: chosen per grid)
-  int target_blocks = 1024;
+  int target_blocks = 0;  // 0: one round of resident workgroups
   int inner_tol_exp = 4;  // FP32 inner CG reduces the residual by 10^-inner_tol_exp
   // geometry each padded work array was last zeroed for (its halo is zero only then)
   std::map<std::string, std::string> geom_key;
@@ -167,6 +167,16 @@ template <class Op>
 int launch_pw(alofdft_ctx* c, const Geom& g, const Op& op) {
   const int nb = pw_blocks(g);
   hipLaunchKernelGGL((k_pointwise<Op, kPointwiseThreads>), dim3(nb), dim3(kPointwiseThreads), 0, c->stream, g, op);
+  CHECK_LAUNCH(c);
+  return nb;
+}
+
+// Second half of a CG iteration: one row per wave, at most kPointwiseBlocks blocks.
+template <typename T>
+int launch_cg_update(alofdft_ctx* c, const Geom& g, const CGP2Op<T>& op) {
+  const int rows = g.ny * g.nz;
+  const int nb = std::max(1, std::min(kPointwiseBlocks, (rows + 3) / 4));
+  hipLaunchKernelGGL((k_cg_update<T, 256>), dim3(nb), dim3(256), 0, c->stream, g, op);
   CHECK_LAUNCH(c);
   return nb;
 }
@@ -355,7 +365,7 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
       pending.push_back({k, pool_used++});
     }
     CGP2Op<T> op2{x, r, pnew, Ap, st, partsA, nb1, (int)k, partsB, T(0)};
-    nprev = launch_pw(c, g, op2);
+    nprev = launch_cg_update(c, g, op2);
     prev = partsB;
     nred_prev = 1;
     if ((k + 1) % check_every == 0) {
@@ -1275,7 +1285,8 @@ void alofdft_destroy(alofdft_ctx* c) {
 }
 
 int alofdft_set_tuning(alofdft_ctx* c, int stencil_variant, int target_blocks, int inner_tol_exp) {
-  if (!c || stencil_variant < -1 || stencil_variant > 4 || target_blocks < 1 || inner_tol_exp < 1 || inner_tol_exp > 7)
+  const bool var_ok = (stencil_variant >= -1 && stencil_variant <= 16) || (stencil_variant >= 100 && stencil_variant <= 116);
+  if (!c || !var_ok || target_blocks < 0 || inner_tol_exp < 1 || inner_tol_exp > 7)
     return ALOFDFT_INVALID_ARGUMENT;
   c->variant = stencil_variant;
   c->target_blocks = target_blocks;

@@ -48,12 +48,22 @@ __device__ inline void block_reduce_store(const double* acc, double* out) {
 }
 
 // Sum over n block partials (stride values apart) of component comp, in a fixed
-// order; every thread of the block returns the same value.
+// order; every thread of the block returns the same value.  Loads go out in
+// batches of 8 per thread, so the sum costs one memory latency per 8 x NT partials.
 template <int NT>
 __device__ inline double block_sum_parts(const double* parts, int n, int stride, int comp) {
   __shared__ double sh[NT / 64];
   double s = 0.0;
-  for (int b = threadIdx.x; b < n; b += NT) s += parts[(long long)b * stride + comp];
+  for (int b0 = threadIdx.x; b0 < n; b0 += 8 * NT) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int b = b0 + u * NT;
+      v[u] = b < n ? parts[(long long)b * stride + comp] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
   __syncthreads();
@@ -210,7 +220,394 @@ __global__ void __launch_bounds__(BX* BY) k_stencil(Geom g, StencilW<T> W, int z
       }
     }
   }
-  if constexpr (NRED > 0) block_reduce_store<NRED, NT>(red, o.parts_out + (long long)blockIdx.x * NRED);
+  if constexpr (NRED > 0) {
+    block_reduce_store<NRED, NT>(red, o.parts_out + (long long)blockIdx.x * NRED);
+  }
+}
+
+// ----------------------------------------------------------------- streaming stencil, buffer addressed
+// Raw buffer access to one grid array: the address is the array base + a per-lane
+// byte offset (VGPR) + a wave-uniform byte offset (SGPR), so the streaming loop
+// needs no per-load address arithmetic.  Arrays must stay below 4 GiB.
+__device__ inline __amdgpu_buffer_rsrc_t brsrc(const void* p, uint32_t nbytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nbytes, 0x00020000);
+}
+template <typename T>
+__device__ inline T bld(const T* p, uint32_t nb, uint32_t vo, uint32_t so);
+template <>
+__device__ inline float bld<float>(const float* p, uint32_t nb, uint32_t vo, uint32_t so) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(brsrc(p, nb), (int)vo, (int)so, 0));
+}
+template <>
+__device__ inline double bld<double>(const double* p, uint32_t nb, uint32_t vo, uint32_t so) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(brsrc(p, nb), (int)vo, (int)so, 0));
+}
+// Stores of the streaming kernel are non-temporal (cache policy nt): the outputs are
+// not read again by the launch, so they should not displace the input planes that
+// neighbouring tiles still read from L2.
+#ifndef ALOFDFT_STORE_POLICY
+#define ALOFDFT_STORE_POLICY 2
+#endif
+template <typename T>
+__device__ inline void bst(T* p, uint32_t nb, uint32_t vo, uint32_t so, T v);
+template <>
+__device__ inline void bst<float>(float* p, uint32_t nb, uint32_t vo, uint32_t so, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), brsrc(p, nb), (int)vo, (int)so,
+                                        ALOFDFT_STORE_POLICY);
+}
+template <>
+__device__ inline void bst<double>(double* p, uint32_t nb, uint32_t vo, uint32_t so, double v) {
+  using u2 = uint32_t __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), brsrc(p, nb), (int)vo, (int)so,
+                                        ALOFDFT_STORE_POLICY);
+}
+
+// Same computation as k_stencil with a different schedule for large planes.  The
+// block is BY waves; wave w owns VY consecutive rows of a 64 x (BY*VY) tile and lane
+// l the column x0 + l, so the row part of every address is wave-uniform and only
+// the lane term is per thread.  The z column of each own node streams through a
+// register queue of K = 2R+1+PD slots (PD planes prefetched ahead); the 2R halo
+// rows of the tile are loaded one row per wave instruction and the 2R*BY*VY x-halo
+// nodes by the first threads, all staged in LDS (double buffered, one barrier per
+// plane).  With alt set, odd z chunks are swept downwards, so the planes two
+// neighbouring chunks share are read by both at about the same time.
+template <typename T, int R, int BY, int VY, int PD, class Op>
+__global__ void __launch_bounds__(64 * BY) k_stencil2(Geom g, StencilW<T> W, int zc, int tiles_x, int tiles_y,
+                                                      int alt, Op op) {
+  constexpr int BX = 64;
+  constexpr int NT = BX * BY;
+  constexpr int TY = BY * VY;
+  constexpr int LX = BX + 2 * R;
+  constexpr int LY = TY + 2 * R;
+  constexpr int K = 2 * R + 1 + PD;
+  constexpr int HR = (2 * R + BY - 1) / BY;  // halo rows per wave
+  constexpr int NXH = 2 * R * TY;            // x-halo nodes per plane
+  constexpr int XH = (NXH + NT - 1) / NT;    // x-halo nodes per thread
+  constexpr int NRED = Op::NRED;
+  constexpr uint32_t ES = sizeof(T);
+  static_assert(K % 2 == 0, "queue length must be even (LDS parity)");
+  __shared__ T lds[2][LY * LX];
+
+  Op o = op;
+  if (!o.template begin<NT>()) return;
+
+  const uint32_t nb = (uint32_t)(g.total * (long long)ES);
+  const int ntile = tiles_x * tiles_y;
+  // chunk-fastest order within each XCD's contiguous range: the chunks of one tile
+  // column run together (their shared z planes meet in L2), and an XCD owns whole
+  // tile columns
+  const int nchunks = gridDim.x / ntile;
+  const int lb = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int tile = lb / nchunks, chunk = lb % nchunks;
+  const int x0 = (tile % tiles_x) * BX, y0 = (tile / tiles_x) * TY;
+  const int zbeg = chunk * zc, zend = min(zbeg + zc, g.nz), len = zend - zbeg;
+  const bool down = alt && (chunk & 1);
+  const int zfirst = down ? zend - 1 : zbeg;
+  const long long pstep = down ? -g.plane : g.plane;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t rowb = (uint32_t)g.px * ES;
+  const uint32_t vl = (uint32_t)lane * ES;
+  // byte offset of node (x0, y0) of logical plane t (plane zfirst + t * direction)
+  const long long org = g.base + (long long)zfirst * g.plane + (long long)y0 * g.px + x0;
+  auto plane_off = [&](int t) -> uint32_t { return (uint32_t)((org + (long long)t * pstep) * ES); };
+  const uint32_t own_row = (uint32_t)(wv * VY) * rowb;
+
+  // halo rows handled by this wave: LDS row and byte offset from row y0 - R
+  int hly[HR];
+  uint32_t hro[HR];
+  bool hok[HR];
+#pragma unroll
+  for (int i = 0; i < HR; ++i) {
+    const int hr = wv + BY * i;
+    hok[i] = hr < 2 * R;
+    const int ly = hr < R ? hr : TY + hr;
+    hly[i] = ly;
+    hro[i] = (uint32_t)ly * rowb;  // row y0 - R + ly, biased by +R rows
+  }
+  // x-halo nodes of this thread: LDS index and byte offset from (x0 - R, y0)
+  int xl[XH];
+  uint32_t xo[XH];
+  bool xok[XH];
+#pragma unroll
+  for (int m = 0; m < XH; ++m) {
+    const int e = threadIdx.x + m * NT;
+    xok[m] = e < NXH;
+    const int r = xok[m] ? e / (2 * R) : 0, c = xok[m] ? e % (2 * R) : 0;
+    const int lx = c < R ? c : BX + c;
+    xl[m] = (R + r) * LX + lx;
+    xo[m] = (uint32_t)((r * g.px + lx) * ES);
+  }
+  const uint32_t rbias = (uint32_t)R * rowb;       // halo rows: offsets carry +R rows
+  const uint32_t xbias = (uint32_t)R * ES;         // x halo: offsets carry +R columns
+
+  T q[K][VY];
+  T hrg[HR];
+  T xrg[XH];
+  double red[NRED > 0 ? NRED : 1];
+#pragma unroll
+  for (int r = 0; r < (NRED > 0 ? NRED : 1); ++r) red[r] = 0.0;
+
+  // queue: logical planes -R .. R+PD-1 into slots 0 .. K-2 (slot of plane t+d at
+  // unrolled step s is (s + R + d) mod K); the last slot is filled by the first prefetch
+#pragma unroll
+  for (int m = 0; m < K - 1; ++m) {
+    const int t = m - R;
+    if (t <= len - 1 + R) {
+      const uint32_t so = plane_off(t) + own_row;
+#pragma unroll
+      for (int v = 0; v < VY; ++v) q[m][v] = o.loadb(nb, vl, so + v * rowb);
+    } else {
+#pragma unroll
+      for (int v = 0; v < VY; ++v) q[m][v] = T(0);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < VY; ++v) q[K - 1][v] = T(0);
+  {
+    const uint32_t so = plane_off(0);
+#pragma unroll
+    for (int i = 0; i < HR; ++i) hrg[i] = hok[i] ? o.loadb(nb, vl, so + hro[i] - rbias) : T(0);
+#pragma unroll
+    for (int m = 0; m < XH; ++m) xrg[m] = xok[m] ? o.loadb(nb, xo[m], so - xbias) : T(0);
+  }
+
+  for (int t0 = 0; t0 < len; t0 += K) {
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+      const int t = t0 + s;
+      if (t < len) {
+        T* L = lds[s & 1];
+#pragma unroll
+        for (int v = 0; v < VY; ++v) L[(R + wv * VY + v) * LX + R + lane] = q[(s + R) % K][v];
+#pragma unroll
+        for (int i = 0; i < HR; ++i)
+          if (hok[i]) L[hly[i] * LX + R + lane] = hrg[i];
+#pragma unroll
+        for (int m = 0; m < XH; ++m)
+          if (xok[m]) L[xl[m]] = xrg[m];
+        if (t + PD <= len - 1) {
+          const uint32_t so = plane_off(t + R + PD) + own_row;
+#pragma unroll
+          for (int v = 0; v < VY; ++v) q[(s + 2 * R + PD) % K][v] = o.loadb(nb, vl, so + v * rowb);
+        }
+        if (t + 1 < len) {
+          const uint32_t so = plane_off(t + 1);
+#pragma unroll
+          for (int i = 0; i < HR; ++i)
+            if (hok[i]) hrg[i] = o.loadb(nb, vl, so + hro[i] - rbias);
+#pragma unroll
+          for (int m = 0; m < XH; ++m)
+            if (xok[m]) xrg[m] = o.loadb(nb, xo[m], so - xbias);
+        }
+        __syncthreads();
+        const uint32_t so = plane_off(t) + own_row;
+        const int z = zfirst + (down ? -t : t);
+#pragma unroll
+        for (int v = 0; v < VY; ++v) {
+          const T* row = L + (R + wv * VY + v) * LX + R + lane;
+          const T c = q[(s + R) % K][v];
+          T acc = W.c0 * c;
+#pragma unroll
+          for (int p = 1; p <= R; ++p) {
+            const int a = v - p, b = v + p;  // own-row index of the y neighbours
+            const T ya = (a >= 0) ? q[(s + R) % K][a >= 0 ? a : 0] : row[-p * LX];
+            const T yb = (b < VY) ? q[(s + R) % K][b < VY ? b : 0] : row[p * LX];
+            acc += W.w[p] * (((q[(s + R - p) % K][v] + q[(s + R + p) % K][v]) + (row[-p] + row[p])) + (ya + yb));
+          }
+          const int gx = x0 + lane, gy = y0 + wv * VY + v;
+          if (gy < g.ny && gx < g.nx) o.storeb(nb, vl, so + v * rowb, gx, gy, z, c, acc, red);
+        }
+      }
+    }
+  }
+  if constexpr (NRED > 0) {
+    block_reduce_store<NRED, NT>(red, o.parts_out + (long long)blockIdx.x * NRED);
+  }
+}
+
+// Forward-accumulating variant of k_stencil2.  Every plane t' of the chunk and its
+// 2R z neighbours is loaded once, PD planes ahead, together with its x/y halo, so a
+// plane and the halo copies of it that the neighbouring tiles read are fetched at
+// about the same time (and meet in L2).  Its z taps are scattered forward into a
+// ring of 2R+2 accumulators -- slot (t + R) mod K holds output plane t, which
+// receives w_|d| u(t + d) from each plane as it arrives -- and its x/y taps are
+// added from LDS when the plane itself is staged; output t is complete, and
+// stored, when plane t + R has arrived.  Same arithmetic per node as k_stencil.
+template <typename T, int R, int BY, int VY, int PD, class Op>
+__global__ void __launch_bounds__(64 * BY) k_stencil3(Geom g, StencilW<T> W, int zc, int tiles_x, int tiles_y,
+                                                      int alt, Op op) {
+  constexpr int BX = 64;
+  constexpr int NT = BX * BY;
+  constexpr int TY = BY * VY;
+  constexpr int LX = BX + 2 * R;
+  constexpr int LY = TY + 2 * R;
+  constexpr int K = 2 * R + 2;               // accumulator ring (even: LDS parity)
+  constexpr int HR = (2 * R + BY - 1) / BY;  // halo rows per wave
+  constexpr int NXH = 2 * R * TY;            // x-halo nodes per plane
+  constexpr int XH = (NXH + NT - 1) / NT;    // x-halo nodes per thread
+  constexpr int NRED = Op::NRED;
+  constexpr uint32_t ES = sizeof(T);
+  static_assert(K % PD == 0, "prefetch sets must divide the ring");
+  __shared__ T lds[2][LY * LX];
+
+  Op o = op;
+  if (!o.template begin<NT>()) return;
+
+  const uint32_t nb = (uint32_t)(g.total * (long long)ES);
+  const int ntile = tiles_x * tiles_y;
+  // chunk-fastest order within each XCD's contiguous range: the chunks of one tile
+  // column run together (their shared z planes meet in L2), and an XCD owns whole
+  // tile columns
+  const int nchunks = gridDim.x / ntile;
+  const int lb = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int tile = lb / nchunks, chunk = lb % nchunks;
+  const int x0 = (tile % tiles_x) * BX, y0 = (tile / tiles_x) * TY;
+  const int zbeg = chunk * zc, zend = min(zbeg + zc, g.nz), len = zend - zbeg;
+  const bool down = alt && (chunk & 1);
+  const int zfirst = down ? zend - 1 : zbeg;
+  const long long pstep = down ? -g.plane : g.plane;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t rowb = (uint32_t)g.px * ES;
+  const uint32_t vl = (uint32_t)lane * ES;
+  const long long org = g.base + (long long)zfirst * g.plane + (long long)y0 * g.px + x0;
+  // byte offset of node (x0, y0) of chunk plane t (t = -R .. len-1+R)
+  auto plane_off = [&](int t) -> uint32_t { return (uint32_t)((org + (long long)t * pstep) * ES); };
+  const uint32_t own_row = (uint32_t)(wv * VY) * rowb;
+
+  int hly[HR];
+  uint32_t hro[HR];
+  bool hok[HR];
+#pragma unroll
+  for (int i = 0; i < HR; ++i) {
+    const int hr = wv + BY * i;
+    hok[i] = hr < 2 * R;
+    const int ly = hr < R ? hr : TY + hr;
+    hly[i] = ly;
+    hro[i] = (uint32_t)ly * rowb;  // row y0 - R + ly, biased by +R rows
+  }
+  int xl[XH];
+  uint32_t xo[XH];
+  bool xok[XH];
+#pragma unroll
+  for (int m = 0; m < XH; ++m) {
+    const int e = threadIdx.x + m * NT;
+    xok[m] = e < NXH;
+    const int r = xok[m] ? e / (2 * R) : 0, c = xok[m] ? e % (2 * R) : 0;
+    const int lx = c < R ? c : BX + c;
+    xl[m] = (R + r) * LX + lx;
+    xo[m] = (uint32_t)((r * g.px + lx) * ES);
+  }
+  const uint32_t rbias = (uint32_t)R * rowb;
+  const uint32_t xbias = (uint32_t)R * ES;
+
+  constexpr bool NEEDC = Op::NEEDC;  // the epilogue uses the centre value (kept R planes)
+  T acc[K][VY];
+  T cen[NEEDC ? K : 1][VY];
+  T own[PD][VY];
+  T hrg[PD][HR];
+  T xrg[PD][XH];
+  double red[NRED > 0 ? NRED : 1];
+#pragma unroll
+  for (int r = 0; r < (NRED > 0 ? NRED : 1); ++r) red[r] = 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int v = 0; v < VY; ++v) acc[k][v] = T(0);
+
+  const int nsteps = len + 2 * R;  // chunk planes t = i - R, i = 0 .. nsteps-1
+  auto fetch = [&](int i, int set) {
+    const int t = i - R;
+    const uint32_t so = plane_off(t);
+#pragma unroll
+    for (int v = 0; v < VY; ++v) own[set][v] = o.loadb(nb, vl, so + own_row + v * rowb);
+    if (t >= 0 && t < len) {
+#pragma unroll
+      for (int h = 0; h < HR; ++h)
+        if (hok[h]) hrg[set][h] = o.loadb(nb, vl, so + hro[h] - rbias);
+#pragma unroll
+      for (int m = 0; m < XH; ++m)
+        if (xok[m]) xrg[set][m] = o.loadb(nb, xo[m], so - xbias);
+    }
+  };
+#pragma unroll
+  for (int d = 0; d < PD; ++d)
+    if (d < nsteps) fetch(d, d);
+
+  for (int i0 = 0; i0 < nsteps; i0 += K) {
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+      const int i = i0 + s;
+      if (i < nsteps) {
+        const int t = i - R;
+        const int set = s % PD;
+        T u[VY];
+#pragma unroll
+        for (int v = 0; v < VY; ++v) u[v] = own[set][v];
+        if constexpr (NEEDC) {
+#pragma unroll
+          for (int v = 0; v < VY; ++v) cen[s][v] = u[v];
+        }
+        const bool staged = t >= 0 && t < len;
+        T* L = lds[s & 1];
+        if (staged) {
+#pragma unroll
+          for (int v = 0; v < VY; ++v) L[(R + wv * VY + v) * LX + R + lane] = u[v];
+#pragma unroll
+          for (int h = 0; h < HR; ++h)
+            if (hok[h]) L[hly[h] * LX + R + lane] = hrg[set][h];
+#pragma unroll
+          for (int m = 0; m < XH; ++m)
+            if (xok[m]) L[xl[m]] = xrg[set][m];
+        }
+        if (i + PD < nsteps) fetch(i + PD, set);
+        // z taps of plane t into outputs t-R .. t+R (slot of output t+d is (s+d) mod K)
+#pragma unroll
+        for (int v = 0; v < VY; ++v) {
+          acc[(s + R) % K][v] = W.w[R] * u[v];
+#pragma unroll
+          for (int d = -R; d < R; ++d) {
+            const T wd = d == 0 ? W.c0 : W.w[d < 0 ? -d : d];
+            acc[(s + d + K) % K][v] += wd * u[v];
+          }
+        }
+        if (staged) {
+          __syncthreads();
+#pragma unroll
+          for (int v = 0; v < VY; ++v) {
+            const T* row = L + (R + wv * VY + v) * LX + R + lane;
+            T xy = T(0);
+#pragma unroll
+            for (int p = 1; p <= R; ++p) {
+              const int a = v - p, b = v + p;
+              const T ya = (a >= 0) ? u[a >= 0 ? a : 0] : row[-p * LX];
+              const T yb = (b < VY) ? u[b < VY ? b : 0] : row[p * LX];
+              xy += W.w[p] * ((row[-p] + row[p]) + (ya + yb));
+            }
+            acc[s % K][v] += xy;
+          }
+        }
+        // output t - R is complete
+        const int to = t - R;
+        if (to >= 0) {
+          const uint32_t so = plane_off(to) + own_row;
+          const int z = zfirst + (down ? -to : to);
+#pragma unroll
+          for (int v = 0; v < VY; ++v) {
+            const int gx = x0 + lane, gy = y0 + wv * VY + v;
+            if (gy < g.ny && gx < g.nx) {
+              const T c = NEEDC ? cen[NEEDC ? (s - R + K) % K : 0][v] : T(0);
+              o.storeb(nb, vl, so + v * rowb, gx, gy, z, c, acc[(s - R + K) % K][v], red);
+            }
+          }
+        }
+      }
+    }
+  }
+  if constexpr (NRED > 0) {
+    block_reduce_store<NRED, NT>(red, o.parts_out + (long long)blockIdx.x * NRED);
+  }
 }
 
 // ----------------------------------------------------------------- pointwise sweep
@@ -230,7 +627,9 @@ __global__ void __launch_bounds__(NT) k_pointwise(Geom g, Op op) {
     const long long rb = g.base + (long long)k * g.plane + (long long)j * g.px;
     for (int i = lane; i < g.nx; i += 64) o.apply(rb + i, i, j, k, red);
   }
-  if constexpr (NRED > 0) block_reduce_store<NRED, NT>(red, o.parts_out + (long long)blockIdx.x * NRED);
+  if constexpr (NRED > 0) {
+    block_reduce_store<NRED, NT>(red, o.parts_out + (long long)blockIdx.x * NRED);
+  }
 }
 
 // Single-block sum of block partials: out[c] = scale * sum_b parts[b*nred + c].
@@ -246,6 +645,7 @@ __global__ void __launch_bounds__(NT) k_finalize(const double* parts, int nparts
 template <typename T>
 struct LapOp {
   static constexpr int NRED = 0;
+  static constexpr bool NEEDC = false;
   const T* x;
   T* y;
   double* parts_out;
@@ -253,14 +653,18 @@ struct LapOp {
   __device__ bool begin() { return true; }
   __device__ T load(long long i) const { return x[i]; }
   __device__ void store(long long i, int, int, int, T, T lap, double*) const { y[i] = lap; }
+  __device__ T loadb(uint32_t nb, uint32_t vo, uint32_t so) const { return bld(x, nb, vo, so); }
+  __device__ void storeb(uint32_t nb, uint32_t vo, uint32_t so, int, int, int, T, T lap, double*) const {
+    bst(y, nb, vo, so, lap);
+  }
 };
 
 // ----------------------------------------------------------------- ops: conjugate gradients
-// A = -(1/4 pi) Delta_h with zero ghosts; the stencil weights carry the -1/4pi.
 // Initial residual r = rhs - A x and, when p is not null, p = r; reduces r.r and rhs.rhs.
 template <typename T>
 struct CGInitOp {
   static constexpr int NRED = 2;
+  static constexpr bool NEEDC = false;
   const T* x;
   const T* rhs;
   T* r;
@@ -277,15 +681,25 @@ struct CGInitOp {
     red[0] += (double)ri * (double)ri;
     red[1] += (double)b * (double)b;
   }
+  __device__ T loadb(uint32_t nb, uint32_t vo, uint32_t so) const { return bld(x, nb, vo, so); }
+  __device__ void storeb(uint32_t nb, uint32_t vo, uint32_t so, int, int, int, T, T ax, double* red) const {
+    const T b = bld(rhs, nb, vo, so);
+    const T ri = b - ax;
+    bst(r, nb, vo, so, ri);
+    if (p) bst(p, nb, vo, so, ri);
+    red[0] += (double)ri * (double)ri;
+    red[1] += (double)b * (double)b;
+  }
 };
 
 // Iteration k, first half: reduce r.r from the previous kernel's partials, stop
-// at r.r <= tol^2 ||rhs||^2, else p_new = r + beta p_old staged on load, Ap = A p_new,
+// at r.r <= tol^2 ||rhs||^2, else p_new = r + beta p_old formed on load, Ap = A p_new,
 // reduce p.Ap.  Block 0 keeps the scalars in CGState (indexed by k parity so no
 // block reads a value written by the same launch).
 template <typename T>
 struct CGP1Op {
   static constexpr int NRED = 1;
+  static constexpr bool NEEDC = true;
   const T* r;
   const T* pold;
   T* pnew;
@@ -337,6 +751,14 @@ struct CGP1Op {
     Ap[i] = ap;
     red[0] += (double)c * (double)ap;
   }
+  __device__ T loadb(uint32_t nb, uint32_t vo, uint32_t so) const {
+    return bld(r, nb, vo, so) + beta * bld(pold, nb, vo, so);
+  }
+  __device__ void storeb(uint32_t nb, uint32_t vo, uint32_t so, int, int, int, T c, T ap, double* red) const {
+    bst(pnew, nb, vo, so, c);
+    bst(Ap, nb, vo, so, ap);
+    red[0] += (double)c * (double)ap;
+  }
 };
 
 // Iteration k, second half: alpha = r.r / p.Ap; x += alpha p; r -= alpha Ap; reduce r.r.
@@ -371,6 +793,52 @@ struct CGP2Op {
     red[0] += (double)ri * (double)ri;
   }
 };
+
+// Second half of a CG iteration (CGP2Op) with one grid row per wave: each lane
+// issues the loads of all its nodes of the row (up to 4 x 64 per pass) before any
+// store, so a row costs one memory latency.
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_cg_update(Geom g, CGP2Op<T> op) {
+  CGP2Op<T> o = op;
+  if (!o.template begin<NT>()) return;
+  double red[1] = {0.0};
+  const int lane = threadIdx.x & 63;
+  const int nwaves = gridDim.x * (NT / 64);
+  const int nrows = g.ny * g.nz;
+  T* __restrict__ x = o.x;
+  T* __restrict__ r = o.r;
+  const T* __restrict__ p = o.p;
+  const T* __restrict__ Ap = o.Ap;
+  const T alpha = o.alpha;
+  for (int row = blockIdx.x * (NT / 64) + (threadIdx.x >> 6); row < nrows; row += nwaves) {
+    const int j = row % g.ny, k = row / g.ny;
+    const long long rb = g.base + (long long)k * g.plane + (long long)j * g.px;
+    for (int i0 = 0; i0 < g.nx; i0 += 4 * 64) {
+      T xv[4], pv[4], rv[4], av[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + lane + 64 * u;
+        if (i < g.nx) {
+          xv[u] = x[rb + i];
+          pv[u] = p[rb + i];
+          rv[u] = r[rb + i];
+          av[u] = Ap[rb + i];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + lane + 64 * u;
+        if (i < g.nx) {
+          x[rb + i] = xv[u] + alpha * pv[u];
+          const T ri = rv[u] - alpha * av[u];
+          r[rb + i] = ri;
+          red[0] += (double)ri * (double)ri;
+        }
+      }
+    }
+  }
+  block_reduce_store<1, NT>(red, o.parts_out + blockIdx.x);
+}
 
 // ----------------------------------------------------------------- ops: density updates
 // Position of node (i,j,k) relative to the box centre.

@@ -20,9 +20,10 @@ struct LaunchCfg {
 // block-partial buffers).
 inline int max_stencil_blocks(const Geom& g, int target) {
   // a launch uses tiles * chunks <= target + 8 * tiles workgroups, with tiles no
-  // more than this count of 32 x 4 tiles
+  // more than this count of 32 x 4 tiles; target 0 (one round of resident
+  // workgroups) stays below 8192 on any part with up to 512 compute units
   const int tiles = ((g.nx + 31) / 32) * ((g.ny + 3) / 4);
-  return target + 8 * tiles + 64;
+  return (target > 0 ? target : 8192) + 8 * tiles + 64;
 }
 
 template <int R, typename T, class Op>

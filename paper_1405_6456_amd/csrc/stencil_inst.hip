@@ -1,4 +1,5 @@
 // Stencil launches for one radius (compiled once per radius with -DALOFDFT_RADIUS=n).
+#include <atomic>
 #include <type_traits>
 
 #include "launch.h"
@@ -8,6 +9,21 @@
 #endif
 
 namespace alofdft {
+
+// Compute units of the current device (every device the library drives is the same
+// part, so the first answer is kept).
+static int cu_count() {
+  static std::atomic<int> n{-1};
+  int v = n.load(std::memory_order_relaxed);
+  if (v < 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                  hipSuccess || v < 1)
+      v = 256;
+    n.store(v, std::memory_order_relaxed);
+  }
+  return v;
+}
 
 // Launch shapes.  Large grids: one contiguous z slab per XCD -- the chunk count is a
 // multiple of 8 and the XCD swizzle of the kernel hands XCD x the chunks
@@ -37,20 +53,118 @@ static hipError_t launch_cfg(const LaunchCfg& lc, const Geom& g, const StencilW<
   return hipGetLastError();
 }
 
+// Streaming kernel k_stencil2: 64 x (BY*VY) tiles, the z extent split into about
+// target / tiles chunks (target 0: as many as one round of resident workgroups
+// holds), odd chunks swept downwards when alt is set.
+template <typename T, int R, int BY, int VY, int PD, class Op>
+static hipError_t launch_cfg2(const LaunchCfg& lc, const Geom& g, const StencilW<T>& W, const Op& op, int* nblocks,
+                              int alt) {
+  constexpr int TY = BY * VY;
+  const int tiles_x = (g.nx + 63) / 64;
+  const int tiles_y = (g.ny + TY - 1) / TY;
+  const int tiles = tiles_x * tiles_y;
+  int nchunks;
+  if (lc.target_blocks > 0) {
+    nchunks = std::max(1, std::min(g.nz, (lc.target_blocks + tiles - 1) / tiles));
+  } else {
+    // one full round of resident workgroups
+    static std::atomic<int> per_cu{-1};
+    int occ = per_cu.load(std::memory_order_relaxed);
+    if (occ < 0) {
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_stencil2<T, R, BY, VY, PD, Op>, 64 * BY, 0) !=
+              hipSuccess ||
+          occ < 1)
+        occ = 1;
+      per_cu.store(occ, std::memory_order_relaxed);
+    }
+    nchunks = std::max(1, std::min(g.nz, occ * cu_count() / tiles));
+  }
+  const int zc = (g.nz + nchunks - 1) / nchunks;
+  nchunks = (g.nz + zc - 1) / zc;
+  const int nb = tiles * nchunks;
+  hipLaunchKernelGGL((k_stencil2<T, R, BY, VY, PD, Op>), dim3(nb), dim3(64 * BY), 0, lc.stream, g, W, zc, tiles_x,
+                     tiles_y, alt, op);
+  *nblocks = nb;
+  return hipGetLastError();
+}
+
+// Forward-accumulating kernel k_stencil3, same tiles and chunks as k_stencil2.
+template <typename T, int R, int BY, int VY, int PD, class Op>
+static hipError_t launch_cfg3(const LaunchCfg& lc, const Geom& g, const StencilW<T>& W, const Op& op, int* nblocks,
+                              int alt) {
+  constexpr int TY = BY * VY;
+  const int tiles_x = (g.nx + 63) / 64;
+  const int tiles_y = (g.ny + TY - 1) / TY;
+  const int tiles = tiles_x * tiles_y;
+  int nchunks;
+  if (lc.target_blocks > 0) {
+    nchunks = std::max(1, std::min(g.nz, (lc.target_blocks + tiles - 1) / tiles));
+  } else {
+    // one full round of resident workgroups
+    static std::atomic<int> per_cu{-1};
+    int occ = per_cu.load(std::memory_order_relaxed);
+    if (occ < 0) {
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_stencil3<T, R, BY, VY, PD, Op>, 64 * BY, 0) !=
+              hipSuccess ||
+          occ < 1)
+        occ = 1;
+      per_cu.store(occ, std::memory_order_relaxed);
+    }
+    nchunks = std::max(1, std::min(g.nz, occ * cu_count() / tiles));
+  }
+  const int zc = (g.nz + nchunks - 1) / nchunks;
+  nchunks = (g.nz + zc - 1) / zc;
+  const int nb = tiles * nchunks;
+  hipLaunchKernelGGL((k_stencil3<T, R, BY, VY, PD, Op>), dim3(nb), dim3(64 * BY), 0, lc.stream, g, W, zc, tiles_x,
+                     tiles_y, alt, op);
+  *nblocks = nb;
+  return hipGetLastError();
+}
+
 template <int R, typename T, class Op>
 hipError_t launch_stencil_r(const LaunchCfg& lc, const Geom& g, const StencilW<T>& W, const Op& op, int* nblocks) {
   // the residual pass carries the XC arithmetic: one node per thread keeps it in registers
   if constexpr (std::is_same_v<Op, GradOp>) {
     return launch_cfg<T, R, 64, 4, 1, false, Op>(lc, g, W, op, nblocks);
   } else {
+    // buffer-addressed streaming kernel (arrays below 4 GiB); variants >= 100 sweep
+    // every chunk upwards
+    const int var = lc.variant >= 100 ? lc.variant - 100 : lc.variant;
+    const int alt = lc.variant >= 100 ? 0 : 1;
+    if ((var < 0 || var >= 5) && g.total * (long long)sizeof(T) < (1ll << 32)) {
+      if constexpr (R == 6) {
+        switch (var) {
+          case 5: return launch_cfg2<T, R, 4, 2, 1, Op>(lc, g, W, op, nblocks, alt);
+          case 6: return launch_cfg2<T, R, 4, 4, 1, Op>(lc, g, W, op, nblocks, alt);
+          case 7: return launch_cfg2<T, R, 4, 2, 3, Op>(lc, g, W, op, nblocks, alt);
+          case 8: return launch_cfg2<T, R, 4, 4, 3, Op>(lc, g, W, op, nblocks, alt);
+          case 9: return launch_cfg2<T, R, 8, 2, 1, Op>(lc, g, W, op, nblocks, alt);
+          case 10: return launch_cfg2<T, R, 2, 8, 1, Op>(lc, g, W, op, nblocks, alt);
+          case 11: return launch_cfg3<T, R, 4, 2, 1, Op>(lc, g, W, op, nblocks, alt);
+          case 12: return launch_cfg3<T, R, 4, 4, 1, Op>(lc, g, W, op, nblocks, alt);
+          case 13: return launch_cfg3<T, R, 4, 2, 2, Op>(lc, g, W, op, nblocks, alt);
+          case 14: return launch_cfg3<T, R, 8, 2, 1, Op>(lc, g, W, op, nblocks, alt);
+          case 15: return launch_cfg3<T, R, 4, 4, 2, Op>(lc, g, W, op, nblocks, alt);
+          case 16: return launch_cfg3<T, R, 8, 4, 1, Op>(lc, g, W, op, nblocks, alt);
+          default: break;
+        }
+      }
+      // automatic: 64 x 8 tiles; the plain FP64 Laplacian of large grids streams
+      // faster with forward accumulation over 64 x 16 tiles, two planes ahead
+      if constexpr (std::is_same_v<Op, LapOp<double>>) {
+        if ((long long)g.nx * g.ny * g.nz >= 150ll * 150 * 150)
+          return launch_cfg3<T, R, 4, 4, 2, Op>(lc, g, W, op, nblocks, alt);
+      }
+      return launch_cfg2<T, R, 4, 2, 1, Op>(lc, g, W, op, nblocks, alt);
+    }
     // automatic shape: small grids 64x4 with deep prefetch, large grids 64x8, two rows per thread
-    if (lc.variant < 0) {
+    if (var < 0) {
       const long long tiles = (long long)((g.nx + 63) / 64) * ((g.ny + 7) / 8);
       if (tiles * g.nz <= lc.target_blocks) return launch_cfg<T, R, 64, 4, 1, true, Op>(lc, g, W, op, nblocks);
       return launch_cfg<T, R, 64, 4, 2, false, Op>(lc, g, W, op, nblocks);
     }
     if constexpr (R == 6) {
-      switch (lc.variant) {
+      switch (var) {
         case 1: return launch_cfg<T, R, 64, 4, 1, true, Op>(lc, g, W, op, nblocks);
         case 2: return launch_cfg<T, R, 64, 8, 1, false, Op>(lc, g, W, op, nblocks);
         case 3: return launch_cfg<T, R, 64, 8, 1, true, Op>(lc, g, W, op, nblocks);

@@ -49,17 +49,35 @@ def test_stencil_fp32_matches_oracle(C, orc, nn):
     assert np.abs(y - ref).max() <= 2e-6 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("tuning", [-1, 0, 1, 2, 3, 4])
-def test_stencil_tile_variants(C, orc, tuning):
+@pytest.mark.parametrize("target", [0, 16, 1024])
+@pytest.mark.parametrize("tuning", [-1, 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 105, 106, 111, 112])
+def test_stencil_tile_variants(C, orc, tuning, target):
+    # ragged in x, y and z; target 16 gives long z chunks (odd ones swept downwards),
+    # target 1024 one-plane chunks
     g = synth.Grid((77, 51, 45), 0.5, (0.0, 0.0, 0.0))
     x = synth.random_field(g, 3)
     ref = orc.laplacian(g, 6, x)
-    C.set_tuning(tuning, 1024, 4)
+    C.set_tuning(tuning, target, 4)
     try:
         y = C.apply_laplacian(dev(x), g.h, 6).cpu().numpy()
     finally:
-        C.set_tuning(-1, 1024, 4)
+        C.set_tuning(-1, 0, 4)
     assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("tuning", [5, 6, 8, 10, 106, 11, 12, 13, 14, 15, 16])
+def test_stencil_tile_variants_fp32(C, orc, tuning):
+    import torch
+
+    g = synth.Grid((77, 51, 45), 0.5, (0.0, 0.0, 0.0))
+    x = synth.random_field(g, 4).astype(np.float32)
+    ref = orc.laplacian(g, 6, x.astype(np.float64))
+    C.set_tuning(tuning, 16, 4)
+    try:
+        y = C.apply_laplacian(dev(x, torch.float32), g.h, 6).cpu().numpy().astype(np.float64)
+    finally:
+        C.set_tuning(-1, 0, 4)
+    assert np.abs(y - ref).max() <= 2e-6 * np.abs(ref).max()
 
 
 def test_stencil_full_size_185(C, orc):
