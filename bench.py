@@ -1,14 +1,22 @@
 """Benchmark: one step = one full ground-state solve of a synthetic Al-like fcc cluster.
 
-Workload (default): 10x10x10 conventional fcc cells, 4000 atoms, a = 7.6 Bohr,
-seeded 0.1 Bohr displacements, 8 Bohr vacuum, h = 0.5 Bohr (185^3 nodes), order-12
+Workload (default, fcc2): 2x2x2 conventional fcc cells, 32 atoms, a = 7.6 Bohr,
+seeded 0.1 Bohr displacements, 8 Bohr vacuum, h = 0.5 Bohr (63^3 nodes), order-12
 stencil, Gaussian pseudocharge (Z = 3, s = 1), TFW + LDA, AL outer loop (eta0 -0.2,
 mu0 1, kappa 0.1), tolerances 1e-8 / 1e-6 / 1e-10.  The timed path solves Poisson
 with FP32 stencil/CG vectors inside FP64 iterative refinement; the plain FP64 GPU
 path is timed once afterwards on the same input for the speedup and the error.
+--workload fcc5 / fcc10 select the 500-atom (109^3) and 4000-atom (185^3) clusters.
 
 Prints one JSON line.  value = stencil grid-point updates per second over the whole
 solve: (FP64 + FP32 stencil applications) x nodes / wall time of the timed steps.
+roofline: the CG stencil pass (p = r + beta p, A p, p.Ap), the dominant kernel, with
+its algorithmic bytes (read r and p, write p and A p) over its mean kernel duration.
+
+Other modes: --mode stencil (stencil throughput only), --mode counters (a short run
+of the refined Poisson solve for hardware-counter passes, followed by a reference
+copy of known size), --mode serve (the request stream through the serving loop),
+--summarize-counters (writes profiles/traffic.json from counter CSVs).
 """
 import argparse
 import json
@@ -26,17 +34,20 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="fcc10", choices=["single", "fcc2", "fcc5", "fcc10"])
+    ap.add_argument("--workload", default="fcc2", choices=["single", "fcc2", "fcc5", "fcc10"])
     ap.add_argument("--precision", default="fp32r", choices=["fp32r", "fp64"])
     ap.add_argument("--no-fp64-ref", action="store_true", help="skip the FP64 comparison solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     ap.add_argument("--sample-every", type=int, default=8, help="CG kernel launches per timed sample")
-    ap.add_argument("--mode", default="solve", choices=["solve", "stencil", "serve"],
-                    help="stencil: only the streaming stencil measurement (for counter profiling); "
-                         "serve: the request stream of fcc 1-3 clusters through the serving loop")
+    ap.add_argument("--mode", default="solve", choices=["solve", "stencil", "counters", "serve"],
+                    help="stencil: only the streaming stencil measurement; counters: a short refined "
+                         "Poisson solve and a reference copy (for counter passes); serve: the request "
+                         "stream of fcc 1-3 clusters through the serving loop")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KEY"),
+                    help="write profiles/traffic.json entry KEY from two rocprofv3 counter CSVs of --mode counters")
     ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
     ap.add_argument("--rate-factor", type=float, default=1.0,
                     help="serve: arrival rate as a multiple of the sequential FP64 service rate")
@@ -47,19 +58,66 @@ def parse():
 def traffic_for(kernel_key):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source; else None."""
-    import hashlib
-
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         data = json.load(f)
-    src = os.path.join(ROOT, "paper_1405_6456_amd", "csrc", "kernels.hip")
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     ent = data.get(kernel_key)
-    if not ent or ent.get("kernels_sha256_16") != digest:
+    if not ent or ent.get("kernels_sha256_16") != kernel_digest():
         return None
     return ent.get("bytes_per_launch")
+
+
+def kernel_digest():
+    """Hash of the kernel sources (a counter summary is valid only for the source it was taken on)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in ("kernels.h", "stencil_inst.hip", "launch.h", "common.h"):
+        with open(os.path.join(ROOT, "paper_1405_6456_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def summarize_counters(fetch_csv, write_csv, key):
+    """HBM bytes per launch of the CG stencil kernel from a FETCH_SIZE pass and a WRITE_SIZE
+    pass (KiB per dispatch) of --mode counters, each scaled by what the same counter reads for
+    the reference copy of 256 MiB in that run.  Updates profiles/traffic.json[key]."""
+    import csv
+
+    def per_kernel(path, counter):
+        out = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return out
+
+    copy_bytes = 256 * 1024 * 1024
+    res = {}
+    for path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
+        pk = per_kernel(path, counter)
+        cg = [v for k, vs in pk.items() if "CGP1Op<float>" in k and "k_stencil" in k for v in vs]
+        cp = [v for k, vs in pk.items() if "elementwise" in k or "copy" in k.lower() for v in vs]
+        cp = [v for v in cp if v > 0.5 * max(cp)] if cp else []
+        if not cg or not cp:
+            raise SystemExit(f"{path}: no CG stencil or copy dispatches with {counter}")
+        kib_cg = sum(cg) / len(cg)
+        kib_copy = sum(cp) / len(cp)
+        scale = copy_bytes / (kib_copy * 1024.0)
+        res[counter] = {"kib_per_dispatch": round(kib_cg, 1), "copy_kib": round(kib_copy, 1),
+                        "scale": round(scale, 4), "bytes": round(kib_cg * 1024.0 * scale)}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    data = json.load(open(path)) if os.path.exists(path) else {}
+    data[key] = {"kernels_sha256_16": kernel_digest(),
+                 "bytes_per_launch": res["FETCH_SIZE"]["bytes"] + res["WRITE_SIZE"]["bytes"],
+                 "read_bytes": res["FETCH_SIZE"]["bytes"], "write_bytes": res["WRITE_SIZE"]["bytes"],
+                 "counters": res}
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    print(json.dumps(data[key]))
 
 
 def cpu_baseline(system, seconds):
@@ -195,8 +253,34 @@ def serve(args):
     print(json.dumps(line), flush=True)
 
 
+def counters_mode(S):
+    """A short refined Poisson solve on the workload grid (the FP32 CG stencil pass is the
+    kernel of interest), then a 256 MiB reference copy whose counter readings scale the
+    byte counters."""
+    import torch
+
+    import paper_1405_6456_amd as lib
+    from paper_1405_6456_amd import synth
+
+    ctx = lib.Context(0)
+    u0 = synth.initial_u(S.grid, S.N)
+    b, _ = ctx.pseudocharge(S)
+    rho = (torch.from_numpy(u0 * u0).to("cuda:0") + b).contiguous()
+    _, its, rel = ctx.poisson(rho, S.grid, precision=lib.FP32_REFINED, tol=1e-10, max_cg=200)
+    torch.cuda.synchronize()
+    src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": S.name, "cg_iters": its, "relres": rel, "reference_copy_bytes": 2 * src.numel() * 8}),
+          flush=True)
+    ctx.close()
+
+
 def main():
     args = parse()
+    if args.summarize_counters:
+        return summarize_counters(*args.summarize_counters)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               f"(the solve is not sharded across GPUs)", file=sys.stderr)
@@ -211,6 +295,8 @@ def main():
     if args.mode == "serve":
         return serve(args)
     S = synth.config(args.workload)
+    if args.mode == "counters":
+        return counters_mode(S)
     if args.mode == "stencil":
         ctx = lib.Context(0)
         for dt in (0, 1):
@@ -259,14 +345,22 @@ def main():
     tr = traffic_for(kernel_key)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
-                "kernel": "k_stencil CG pass (p = r + beta p, A p, p.Ap)",
+                "kernel": "CG stencil pass (p = r + beta p, A p, p.Ap): k_stencil2 CGP1Op",
                 "alg_bytes_per_launch": alg_bytes, "mean_launch_ms": round(mean_ms, 5), "timed_launches": launches}
 
     # streaming stencil throughput (six rotating buffer pairs, more than the 256 MB cache)
     st_ms = ctx.bench_stencil(S.grid.n, 6, 1 if esize == 4 else 0, reps=100, nbuf=6)
-    stencil = {"gpts": round(npts / (st_ms * 1e-3) / 1e9, 1),
+    stencil = {"nodes": npts, "gpts": round(npts / (st_ms * 1e-3) / 1e9, 1),
                "hbm_frac": round(npts * 2 * esize / (st_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                "dtype": "f32" if esize == 4 else "f64"}
+    # and on the 4000-atom cluster's grid (185^3), both precisions (x read once, y written once)
+    big = synth.config("fcc10").grid.n
+    nbig = big[0] * big[1] * big[2]
+    stencil_185 = {}
+    for dt, name, es in ((0, "f64", 8), (1, "f32", 4)):
+        ms_b = ctx.bench_stencil(big, 6, dt, reps=50, nbuf=6)
+        stencil_185[name] = {"gpts": round(nbig / (ms_b * 1e-3) / 1e9, 1),
+                             "hbm_frac": round(nbig * 2 * es / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     extra = {}
     if not args.no_fp64_ref and prec == lib.FP32_REFINED:
@@ -305,6 +399,7 @@ def main():
         "counts": {k: last[k] for k in ("outer", "inner", "grad_evals", "poisson_solves", "cg_iters", "matvec_fp64",
                                         "matvec_fp32", "refinements")},
         "stencil_streaming": stencil,
+        "stencil_streaming_185": stencil_185,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

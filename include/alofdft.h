@@ -235,9 +235,10 @@ int alofdft_set_tuning(alofdft_ctx* ctx, int stencil_variant, int target_blocks,
 
 /* Measurement of the dominant kernel.  With sample_every > 0, every
  * sample_every-th launch of the conjugate-gradient stencil kernel (the fused
- * p = r + beta p, A p and p.Ap pass of each CG iteration) is bracketed by HIP
- * events on the context stream; launches made after a solve has converged (which
- * exit at once) are not counted.  sample_every = 0 stops sampling.  Calling it
+ * p = r + beta p, A p and p.Ap pass of each CG iteration) carries a pair of HIP
+ * events that the runtime stamps with the start and end of the kernel itself
+ * (hipExtLaunchKernel), so the mean is the kernel duration a kernel trace reports;
+ * launches made after a solve has converged (which exit at once) are not counted.  sample_every = 0 stops sampling.  Calling it
  * resets the statistics.  INVALID_ARGUMENT for a null context or a negative value. */
 int alofdft_profile_cg_kernel(alofdft_ctx* ctx, int sample_every);
 

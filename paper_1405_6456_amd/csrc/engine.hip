@@ -182,8 +182,9 @@ int launch_cg_update(alofdft_ctx* c, const Geom& g, const CGP2Op<T>& op) {
 }
 
 template <typename T, class Op>
-int launch_stencil(alofdft_ctx* c, const Geom& g, const StencilW<T>& W, const Op& op) {
-  const LaunchCfg lc{c->stream, c->variant, c->target_blocks};
+int launch_stencil(alofdft_ctx* c, const Geom& g, const StencilW<T>& W, const Op& op, hipEvent_t ev_start = nullptr,
+                   hipEvent_t ev_stop = nullptr) {
+  const LaunchCfg lc{c->stream, c->variant, c->target_blocks, ev_start, ev_stop};
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (g.R) {
@@ -350,6 +351,7 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
     T* pnew = (k & 1) ? p0 : p1;
     CGP1Op<T> op1{r, pold, pnew, Ap, st, prev, nprev, nred_prev, (int)k, tol2, partsA, T(0)};
     const bool timed = c->prof_every > 0 && k % c->prof_every == 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
       if (pool_used == c->prof_pool.size()) {
         hipEvent_t a, b;
@@ -357,13 +359,11 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
         HIPC(c, hipEventCreate(&b));
         c->prof_pool.push_back({a, b});
       }
-      HIPC(c, hipEventRecord(c->prof_pool[pool_used].first, c->stream));
+      e0 = c->prof_pool[pool_used].first;
+      e1 = c->prof_pool[pool_used].second;
     }
-    const int nb1 = launch_stencil(c, g, A, op1);
-    if (timed) {
-      HIPC(c, hipEventRecord(c->prof_pool[pool_used].second, c->stream));
-      pending.push_back({k, pool_used++});
-    }
+    const int nb1 = launch_stencil(c, g, A, op1, e0, e1);  // events stamp the kernel itself
+    if (timed) pending.push_back({k, pool_used++});
     CGP2Op<T> op2{x, r, pnew, Ap, st, partsA, nb1, (int)k, partsB, T(0)};
     nprev = launch_cg_update(c, g, op2);
     prev = partsB;

@@ -2,6 +2,7 @@
 // radius are compiled in their own translation unit (stencil_inst.hip).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -13,8 +14,21 @@ namespace alofdft {
 struct LaunchCfg {
   hipStream_t stream;
   int variant;        // tile shape (order 12 only; other orders use variant 0)
-  int target_blocks;  // workgroups per launch to aim for (sets the z chunk length)
+  int target_blocks;  // workgroups per launch to aim for (sets the z chunk length); 0: one round
+  hipEvent_t ev_start = nullptr;  // optional: set to the start and end of the kernel itself
+  hipEvent_t ev_stop = nullptr;
 };
+
+// Kernel launch on lc.stream; with events set, the runtime stamps them with the
+// kernel's own start and end (not the surrounding queue packets).
+template <typename K, typename... A>
+inline hipError_t launch_kernel(const LaunchCfg& lc, K kernel, dim3 grid, dim3 block, A... args) {
+  if (lc.ev_start)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, lc.stream, lc.ev_start, lc.ev_stop, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, 0, lc.stream, args...);
+  return hipGetLastError();
+}
 
 // Largest number of workgroups any stencil launch can use on geometry g (sizes the
 // block-partial buffers).

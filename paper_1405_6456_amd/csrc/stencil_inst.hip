@@ -47,10 +47,9 @@ static hipError_t launch_cfg(const LaunchCfg& lc, const Geom& g, const StencilW<
   const int zc = (g.nz + nchunks - 1) / nchunks;
   nchunks = (g.nz + zc - 1) / zc;
   const int nb = tiles * nchunks;
-  hipLaunchKernelGGL((k_stencil<T, R, BX, BY, VY, DEEP, Op>), dim3(nb), dim3(BX * BY), 0, lc.stream, g, W, zc,
-                     tiles_x, tiles_y, op);
   *nblocks = nb;
-  return hipGetLastError();
+  return launch_kernel(lc, k_stencil<T, R, BX, BY, VY, DEEP, Op>, dim3(nb), dim3(BX * BY), g, W, zc, tiles_x, tiles_y,
+                       op);
 }
 
 // Streaming kernel k_stencil2: 64 x (BY*VY) tiles, the z extent split into about
@@ -82,10 +81,9 @@ static hipError_t launch_cfg2(const LaunchCfg& lc, const Geom& g, const StencilW
   const int zc = (g.nz + nchunks - 1) / nchunks;
   nchunks = (g.nz + zc - 1) / zc;
   const int nb = tiles * nchunks;
-  hipLaunchKernelGGL((k_stencil2<T, R, BY, VY, PD, Op>), dim3(nb), dim3(64 * BY), 0, lc.stream, g, W, zc, tiles_x,
-                     tiles_y, alt, op);
   *nblocks = nb;
-  return hipGetLastError();
+  return launch_kernel(lc, k_stencil2<T, R, BY, VY, PD, Op>, dim3(nb), dim3(64 * BY), g, W, zc, tiles_x, tiles_y, alt,
+                       op);
 }
 
 // Forward-accumulating kernel k_stencil3, same tiles and chunks as k_stencil2.
@@ -115,10 +113,9 @@ static hipError_t launch_cfg3(const LaunchCfg& lc, const Geom& g, const StencilW
   const int zc = (g.nz + nchunks - 1) / nchunks;
   nchunks = (g.nz + zc - 1) / zc;
   const int nb = tiles * nchunks;
-  hipLaunchKernelGGL((k_stencil3<T, R, BY, VY, PD, Op>), dim3(nb), dim3(64 * BY), 0, lc.stream, g, W, zc, tiles_x,
-                     tiles_y, alt, op);
   *nblocks = nb;
-  return hipGetLastError();
+  return launch_kernel(lc, k_stencil3<T, R, BY, VY, PD, Op>, dim3(nb), dim3(64 * BY), g, W, zc, tiles_x, tiles_y, alt,
+                       op);
 }
 
 template <int R, typename T, class Op>
