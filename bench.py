@@ -10,8 +10,9 @@ path is timed once afterwards on the same input for the speedup and the error.
 
 Prints one JSON line.  value = stencil grid-point updates per second over the whole
 solve: (FP64 + FP32 stencil applications) x nodes / wall time of the timed steps.
-roofline: the CG stencil pass (p = r + beta p, A p, p.Ap), the dominant kernel, with
-its algorithmic bytes (read r and p, write p and A p) over its mean kernel duration.
+roofline: the first half of each CG iteration (stencil of r; p and A p updated by
+linearity; p.Ap), the dominant kernel, with its algorithmic bytes (read r, p and A p,
+write p and A p) over its mean kernel duration.
 
 Other modes: --mode stencil (stencil throughput only), --mode counters (a short run
 of the refined Poisson solve for hardware-counter passes, followed by a reference
@@ -99,7 +100,7 @@ def summarize_counters(fetch_csv, write_csv, key):
     res = {}
     for path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
         pk = per_kernel(path, counter)
-        cg = [v for k, vs in pk.items() if "CGP1Op<float>" in k and "k_stencil" in k for v in vs]
+        cg = [v for k, vs in pk.items() if "CGP1LOp<float>" in k and "k_stencil" in k for v in vs]
         cp = [v for k, vs in pk.items() if "elementwise" in k or "copy" in k.lower() for v in vs]
         cp = [v for v in cp if v > 0.5 * max(cp)] if cp else []
         if not cg or not cp:
@@ -338,14 +339,15 @@ def main():
     ms_per_step = 1e3 * wall / args.steps
     value = mv * npts / wall / 1e9
     esize = 4 if prec == lib.FP32_REFINED else 8
-    # algorithmic bytes of the CG stencil kernel per node: read r and p, write p and A p
-    alg_bytes = 4 * esize * kpts
+    # algorithmic bytes of the CG stencil kernel per node: read r (stencil input), p and
+    # A p; write p and A p (the first half of each iteration, by linearity)
+    alg_bytes = 5 * esize * kpts
     achieved = alg_bytes / (mean_ms * 1e-3) / 1e9 if mean_ms > 0 else 0.0
     kernel_key = f"cg_stencil_{'f32' if esize == 4 else 'f64'}_{args.workload}"
     tr = traffic_for(kernel_key)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
-                "kernel": "CG stencil pass (p = r + beta p, A p, p.Ap): k_stencil2 CGP1Op",
+                "kernel": "CG first half (A r; p = r + beta p, A p = A r + beta A p; p.Ap): k_stencil2 CGP1LOp",
                 "alg_bytes_per_launch": alg_bytes, "mean_launch_ms": round(mean_ms, 5), "timed_launches": launches}
 
     # streaming stencil throughput (six rotating buffer pairs, more than the 256 MB cache)

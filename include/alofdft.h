@@ -233,9 +233,21 @@ int alofdft_bench_stencil(alofdft_ctx* ctx, const int n[3], int fd_half_width, i
  * those ranges.  Every variant computes the same stencil; they differ in speed. */
 int alofdft_set_tuning(alofdft_ctx* ctx, int stencil_variant, int target_blocks, int inner_tol_exp);
 
+/* Schedule of the conjugate-gradient iterations of every Poisson solve of the
+ * context (Sec. 4: the discrete Poisson problem solved by CG).  Each iteration is
+ * two launches; the second is x += alpha p, r -= alpha A p and r.r.  The first:
+ *   0  p = r + beta p formed on load (the stencil input is r and p over every
+ *      tile's halo), A p by the stencil, p.Ap;
+ *   1  (default) A r by the stencil (one input array), then p = r + beta p and
+ *      A p = A r + beta A p updated in place at each node, p.Ap.
+ * Both stop on the same relative residual of r; their iterates differ by rounding.
+ * INVALID_ARGUMENT for a null context or another value. */
+int alofdft_set_cg_schedule(alofdft_ctx* ctx, int schedule);
+
 /* Measurement of the dominant kernel.  With sample_every > 0, every
  * sample_every-th launch of the conjugate-gradient stencil kernel (the fused
- * p = r + beta p, A p and p.Ap pass of each CG iteration) carries a pair of HIP
+ * first launch of each CG iteration: A r, p, A p and p.Ap with schedule 1, the
+ * default; p = r + beta p, A p and p.Ap with schedule 0) carries a pair of HIP
  * events that the runtime stamps with the start and end of the kernel itself
  * (hipExtLaunchKernel), so the mean is the kernel duration a kernel trace reports;
  * launches made after a solve has converged (which exit at once) are not counted.  sample_every = 0 stops sampling.  Calling it

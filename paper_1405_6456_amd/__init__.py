@@ -89,6 +89,7 @@ def lib():
         L.alofdft_destroy.argtypes = [_VP]
         L.alofdft_destroy.restype = None
         L.alofdft_set_tuning.argtypes = [_VP, C.c_int, C.c_int, C.c_int]
+        L.alofdft_set_cg_schedule.argtypes = [_VP, C.c_int]
         L.alofdft_solve.argtypes = [_VP, C.POINTER(SystemS), C.POINTER(Params), _DP, _DP, _DP, _DP,
                                     C.POINTER(Result)]
         L.alofdft_solve_device.argtypes = [_VP, C.POINTER(SystemS), C.POINTER(Params), _VP, _VP, _VP, _DP,
@@ -187,6 +188,11 @@ class Context:
         _check(self, lib().alofdft_set_tuning(self.handle, variant, target_blocks, inner_tol_exp))
 
     # ------------------------------------------------------------- full solve
+    def set_cg_schedule(self, schedule=1):
+        """First half of each CG iteration: 0 applies the stencil to p = r + beta p;
+        1 (default) applies it to r and forms A p = A r + beta A p by linearity."""
+        _check(self, lib().alofdft_set_cg_schedule(self.handle, int(schedule)))
+
     def solve(self, system, params: Params | None = None, u0=None, want_fields=True, want_forces=True):
         """Ground state on the GPU.  u0: host numpy array (grid shape) or None for the
         library's default guess.  Returns a dict of energies, counters, u, phi, forces."""

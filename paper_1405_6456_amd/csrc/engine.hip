@@ -41,6 +41,7 @@ struct alofdft_ctx {
   int variant = -1;       // stencil tile variant (-1: chosen per grid)
   int target_blocks = 0;  // 0: one round of resident workgroups
   int inner_tol_exp = 4;  // FP32 inner CG reduces the residual by 10^-inner_tol_exp
+  int cg_schedule = 1;    // first half of each CG iteration: 0 stencil of p, 1 stencil of r (linearity)
   // geometry each padded work array was last zeroed for (its halo is zero only then)
   std::map<std::string, std::string> geom_key;
   // sampled event timing of the CG stencil kernel (index 0: FP64, 1: FP32)
@@ -350,6 +351,7 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
     T* pold = (k & 1) ? p1 : p0;
     T* pnew = (k & 1) ? p0 : p1;
     CGP1Op<T> op1{r, pold, pnew, Ap, st, prev, nprev, nred_prev, (int)k, tol2, partsA, T(0)};
+    if (c->cg_schedule == 1) op1.pold = op1.pnew = p0;  // p and A p updated in place
     const bool timed = c->prof_every > 0 && k % c->prof_every == 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
@@ -362,9 +364,10 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
       e0 = c->prof_pool[pool_used].first;
       e1 = c->prof_pool[pool_used].second;
     }
-    const int nb1 = launch_stencil(c, g, A, op1, e0, e1);  // events stamp the kernel itself
+    const int nb1 = c->cg_schedule == 1 ? launch_stencil(c, g, A, CGP1LOp<T>{op1}, e0, e1)
+                                        : launch_stencil(c, g, A, op1, e0, e1);  // events stamp the kernel itself
     if (timed) pending.push_back({k, pool_used++});
-    CGP2Op<T> op2{x, r, pnew, Ap, st, partsA, nb1, (int)k, partsB, T(0)};
+    CGP2Op<T> op2{x, r, op1.pnew, Ap, st, partsA, nb1, (int)k, partsB, T(0)};
     nprev = launch_cg_update(c, g, op2);
     prev = partsB;
     nred_prev = 1;
@@ -385,7 +388,12 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
     T* pold = (k & 1) ? p1 : p0;
     T* pnew = (k & 1) ? p0 : p1;
     CGP1Op<T> op1{r, pold, pnew, Ap, st, prev, nprev, nred_prev, (int)k, tol2, partsA, T(0)};
-    launch_stencil(c, g, A, op1);
+    if (c->cg_schedule == 1) {
+      op1.pold = op1.pnew = p0;
+      launch_stencil(c, g, A, CGP1LOp<T>{op1});
+    } else {
+      launch_stencil(c, g, A, op1);
+    }
     HIPC(c, hipMemcpyAsync(c->pin, st, sizeof(CGState), hipMemcpyDeviceToHost, c->stream));
     sync(c);
     s = *(CGState*)c->pin;
@@ -1291,6 +1299,12 @@ int alofdft_set_tuning(alofdft_ctx* c, int stencil_variant, int target_blocks, i
   c->variant = stencil_variant;
   c->target_blocks = target_blocks;
   c->inner_tol_exp = inner_tol_exp;
+  return ALOFDFT_OK;
+}
+
+int alofdft_set_cg_schedule(alofdft_ctx* c, int schedule) {
+  if (!c || schedule < 0 || schedule > 1) return ALOFDFT_INVALID_ARGUMENT;
+  c->cg_schedule = schedule;
   return ALOFDFT_OK;
 }
 

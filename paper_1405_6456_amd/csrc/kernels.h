@@ -761,6 +761,41 @@ struct CGP1Op {
   }
 };
 
+// Iteration k, first half by linearity: the stencil is applied to r alone and
+// A p_new = A r + beta A p_old (p_new = r + beta p_old), so the stencil input is
+// one array and p and A p are read and written only at the node itself (in
+// place).  Same scalars and verdicts as CGP1Op, whose prologue it shares.  A p is
+// then a recurrence; its rounding is damped by beta < 1 and the solve's stopping
+// test uses the residual r itself.
+template <typename T>
+struct CGP1LOp : CGP1Op<T> {
+  static constexpr bool NEEDC = true;
+  using CGP1Op<T>::r;
+  using CGP1Op<T>::pnew;
+  using CGP1Op<T>::Ap;
+  using CGP1Op<T>::k;
+  using CGP1Op<T>::beta;
+  __device__ T load(long long i) const { return r[i]; }
+  __device__ void store(long long i, int, int, int, T c, T ar, double* red) const {
+    const T pn = k == 0 ? c : c + beta * pnew[i];
+    const T apn = k == 0 ? ar : ar + beta * Ap[i];
+    pnew[i] = pn;
+    Ap[i] = apn;
+    red[0] += (double)pn * (double)apn;
+  }
+  __device__ T loadb(uint32_t nb, uint32_t vo, uint32_t so) const { return bld(r, nb, vo, so); }
+  __device__ void storeb(uint32_t nb, uint32_t vo, uint32_t so, int, int, int, T c, T ar, double* red) const {
+    T pn = c, apn = ar;
+    if (k != 0) {
+      pn = c + beta * bld((const T*)pnew, nb, vo, so);
+      apn = ar + beta * bld((const T*)Ap, nb, vo, so);
+    }
+    bst(pnew, nb, vo, so, pn);
+    bst(Ap, nb, vo, so, apn);
+    red[0] += (double)pn * (double)apn;
+  }
+};
+
 // Iteration k, second half: alpha = r.r / p.Ap; x += alpha p; r -= alpha Ap; reduce r.r.
 template <typename T>
 struct CGP2Op {

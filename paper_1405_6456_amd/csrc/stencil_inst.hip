@@ -119,7 +119,29 @@ static hipError_t launch_cfg3(const LaunchCfg& lc, const Geom& g, const StencilW
 }
 
 template <int R, typename T, class Op>
+hipError_t launch_stencil_plain(const LaunchCfg& lc, const Geom& g, const StencilW<T>& W, const Op& op, int* nblocks);
+
+template <class Op>
+struct is_cg_linear : std::false_type {};
+template <typename T>
+struct is_cg_linear<CGP1LOp<T>> : std::true_type {};
+
+template <int R, typename T, class Op>
 hipError_t launch_stencil_r(const LaunchCfg& lc, const Geom& g, const StencilW<T>& W, const Op& op, int* nblocks) {
+  // the CG first half by linearity: streaming kernel over 64x8 tiles (forward
+  // accumulation for variants 11..16)
+  if constexpr (is_cg_linear<Op>::value) {
+    const int var = lc.variant >= 100 ? lc.variant - 100 : lc.variant;
+    const int alt = lc.variant >= 100 ? 0 : 1;
+    if (var >= 11 && var <= 16) return launch_cfg3<T, R, 4, 2, 1, Op>(lc, g, W, op, nblocks, alt);
+    return launch_cfg2<T, R, 4, 2, 1, Op>(lc, g, W, op, nblocks, alt);
+  } else {
+    return launch_stencil_plain<R, T, Op>(lc, g, W, op, nblocks);
+  }
+}
+
+template <int R, typename T, class Op>
+hipError_t launch_stencil_plain(const LaunchCfg& lc, const Geom& g, const StencilW<T>& W, const Op& op, int* nblocks) {
   // the residual pass carries the XC arithmetic: one node per thread keeps it in registers
   if constexpr (std::is_same_v<Op, GradOp>) {
     return launch_cfg<T, R, 64, 4, 1, false, Op>(lc, g, W, op, nblocks);
@@ -183,6 +205,8 @@ ALOFDFT_INST(float, CGInitOp<float>)
 ALOFDFT_INST(double, CGP1Op<double>)
 ALOFDFT_INST(float, CGP1Op<float>)
 ALOFDFT_INST(double, GradOp)
+ALOFDFT_INST(double, CGP1LOp<double>)
+ALOFDFT_INST(float, CGP1LOp<float>)
 #undef ALOFDFT_INST
 
 }  // namespace alofdft

@@ -46,6 +46,7 @@ def test_host_only_calls():
     assert p.tol_constraint == 1e-8 and p.tol_grad == 1e-6 and p.tol_poisson == 1e-10
     assert L.alofdft_default_params(None) == lib.INVALID_ARGUMENT
     assert L.alofdft_set_tuning(None, 0, 1024, 4) == lib.INVALID_ARGUMENT
+    assert L.alofdft_set_cg_schedule(None, 1) == lib.INVALID_ARGUMENT
 
 
 def test_binding_refuses_without_gpu():

@@ -113,14 +113,39 @@ def _gauss_rho(g, charges):
 
 @pytest.mark.parametrize("bc", [0, 1])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_poisson_matches_oracle(C, orc, bc, precision):
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_poisson_matches_oracle(C, orc, bc, precision, schedule):
+    # both CG schedules (stencil of p; stencil of r with A p by linearity) reach the oracle's solution
     g = synth.Grid((41, 38, 35), 0.45, (-9.0, -8.3, -7.6))
     rho = _gauss_rho(g, [(1.0, (0.3, -0.4, 0.2), 1.0), (-0.7, (-1.1, 0.8, -0.3), 0.9)])
     rhs = orc.poisson_rhs(g, 6, bc, rho)
     ref, _, _, _ = orc.poisson_cg(g, 6, rhs, tol=1e-13)
-    phi, its, rel = C.poisson(dev(rho), g, bc=bc, precision=precision, tol=1e-11)
+    C.set_cg_schedule(schedule)
+    try:
+        phi, its, rel = C.poisson(dev(rho), g, bc=bc, precision=precision, tol=1e-11)
+    finally:
+        C.set_cg_schedule(1)
     assert rel < 1e-11
     assert np.abs(phi.cpu().numpy() - ref).max() <= 1e-8 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_poisson_iteration_cap(C, schedule):
+    # stopped by the cap: exactly max_cg iterations and the true relative residual of the last iterate
+    import torch
+
+    g = synth.Grid((40, 36, 33), 0.5, (0.0, 0.0, 0.0))
+    rho = torch.from_numpy(synth.random_field(g, 21)).cuda()
+    C.set_cg_schedule(schedule)
+    try:
+        phi, its, rel = C.poisson(rho, g, bc=0, tol=1e-14, max_cg=37)
+    finally:
+        C.set_cg_schedule(1)
+    assert its == 37
+    # residual of the returned phi, recomputed with the stencil
+    A_phi = -C.apply_laplacian(phi, g.h, 6) / (4 * math.pi)
+    true_rel = float(torch.linalg.norm(rho - A_phi) / torch.linalg.norm(rho))
+    assert abs(true_rel - rel) <= 1e-6 * true_rel + 1e-12
 
 
 def test_poisson_gaussian_closed_form(C):
