@@ -229,7 +229,7 @@ int alofdft_bench_stencil(alofdft_ctx* ctx, const int n[3], int fd_half_width, i
  * target_blocks is the number of stencil workgroups to aim for (it sets the z
  * chunk length); 0 fills one round of the workgroups the device holds at once.
  * inner_tol_exp is the FP32 inner-solve residual reduction 10^-inner_tol_exp of
- * the refined Poisson solve (1..7).  Defaults -1, 0, 4.  INVALID_ARGUMENT outside
+ * the refined Poisson solve (1..7).  Defaults -1, 0, 6.  INVALID_ARGUMENT outside
  * those ranges.  Every variant computes the same stencil; they differ in speed. */
 int alofdft_set_tuning(alofdft_ctx* ctx, int stencil_variant, int target_blocks, int inner_tol_exp);
 

@@ -184,7 +184,7 @@ class Context:
         except Exception:
             pass
 
-    def set_tuning(self, variant=-1, target_blocks=0, inner_tol_exp=4):
+    def set_tuning(self, variant=-1, target_blocks=0, inner_tol_exp=6):
         _check(self, lib().alofdft_set_tuning(self.handle, variant, target_blocks, inner_tol_exp))
 
     # ------------------------------------------------------------- full solve

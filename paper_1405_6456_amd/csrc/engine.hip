@@ -40,7 +40,7 @@ struct alofdft_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int variant = -1;       // stencil tile variant (-1: chosen per grid)
   int target_blocks = 0;  // 0: one round of resident workgroups
-  int inner_tol_exp = 4;  // FP32 inner CG reduces the residual by 10^-inner_tol_exp
+  int inner_tol_exp = 6;  // FP32 inner CG reduces the residual by 10^-inner_tol_exp
   int cg_schedule = 1;    // first half of each CG iteration: 0 stencil of p, 1 stencil of r (linearity)
   // geometry each padded work array was last zeroed for (its halo is zero only then)
   std::map<std::string, std::string> geom_key;
@@ -304,7 +304,7 @@ struct CGResult {
 template <typename T>
 CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* rhs, T* x, double tol, long long max_it,
                   int check_every, const char* tag, bool init = true, const double* init_parts = nullptr,
-                  int init_nparts = 0) {
+                  int init_nparts = 0, bool stop_on_stagnation = false) {
   const std::string t(tag);
   T* r = gridbuf<T>(c, t + ".r", g);
   T* p0 = gridbuf<T>(c, t + ".p0", g);
@@ -346,6 +346,8 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
     pool_used = 0;
   };
   long long k = 0;
+  double best_rr = HUGE_VAL;
+  long long best_k = 0;
   for (;; ++k) {
     if (k >= max_it) break;
     T* pold = (k & 1) ? p1 : p0;
@@ -377,6 +379,17 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
       const CGState* sp = (CGState*)c->pin;
       harvest(sp->done ? sp->iter : k + 1);
       if (sp->done) break;
+      if (stop_on_stagnation) {
+        // rounding-limited (FP32) solve: give up when r.r has not halved in 256 iterations
+        const double rr = sp->rrh[sp->iter & 1];
+        if (rr < 0.5 * best_rr) {
+          best_rr = rr;
+          best_k = k;
+        } else if (k - best_k >= 256) {
+          ++k;
+          break;
+        }
+      }
     }
   }
   // one more half iteration to test the last residual if the loop ended without a verdict
@@ -467,7 +480,7 @@ PoissonStats poisson(alofdft_ctx* c, const Geom& g, int fdn, double h, int preci
     // aim below the outer tolerance without asking FP32 for more than it can give
     const double want = std::max(inner_tol, 0.5 * tol / ps.relres);
     CGResult ir = cg_solve<float>(c, g, A32, nullptr, x32, want, max_cg - ps.iters, check_every, "cg32", false,
-                                  partsF, nbf);
+                                  partsF, nbf, true);
     ps.iters += ir.iters;
     ps.mv32 += ir.iters;
     if (ir.done == 2) { ps.status = ALOFDFT_NUMERICAL; return ps; }

@@ -66,3 +66,28 @@ def test_workload_matches_oracle_fixture(C, name, precision):
     u = out["u"]
     us = np.array([u[k, j, i] for i, j, k in gold["sample_nodes"]])
     assert np.abs(us - np.array(gold["u_samples"])).max() < 1e-4 * np.abs(u).max()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fcc5_solution_is_the_oracle_minimiser(C, orc, precision):
+    # 500 atoms, 109^3 nodes: instead of a full oracle minimisation (hours on the host),
+    # check the defining property of the result with the oracle's own arithmetic.  The
+    # discrete minimiser under C_h(u) = 0 is unique; at the GPU's u* with its multiplier
+    # eta*, the oracle's residual of the Euler-Lagrange equation (Sec. 4, mu term off)
+    # must vanish to the solver's tolerance, and the oracle's energy and Hellmann-Feynman
+    # forces at u* must equal the GPU's.  An energy error of the minimiser is then of
+    # order ||g||^2, far below 1e-6 Ha/atom.
+    import paper_1405_6456_amd as lib
+
+    S = synth.config("fcc5")
+    out = C.solve(S, lib.default_params(precision=precision), synth.initial_u(S.grid, S.N))
+    assert out["status"] == 0
+    assert abs(out["C_h"]) / S.N < 1e-8
+    prm = orc.params()
+    g, e, phi_o, _ = orc.evaluate(S, prm, out["u"], eta=out["eta_star"], mu=0.0, phi=out["phi"])
+    h3 = S.grid.h ** 3
+    gnorm = float(np.sqrt(h3 * np.sum(g * g)))
+    assert gnorm < 1e-5
+    assert abs(e["E_total"] - out["E_total"]) / S.M < 1e-9
+    f_o = orc.forces(S, prm, phi_o)
+    assert np.abs(f_o - out["forces"]).max() < 1e-6

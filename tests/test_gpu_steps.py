@@ -61,7 +61,7 @@ def test_stencil_tile_variants(C, orc, tuning, target):
     try:
         y = C.apply_laplacian(dev(x), g.h, 6).cpu().numpy()
     finally:
-        C.set_tuning(-1, 0, 4)
+        C.set_tuning(-1, 0, 6)
     assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
@@ -76,7 +76,7 @@ def test_stencil_tile_variants_fp32(C, orc, tuning):
     try:
         y = C.apply_laplacian(dev(x, torch.float32), g.h, 6).cpu().numpy().astype(np.float64)
     finally:
-        C.set_tuning(-1, 0, 4)
+        C.set_tuning(-1, 0, 6)
     assert np.abs(y - ref).max() <= 2e-6 * np.abs(ref).max()
 
 
