@@ -139,7 +139,9 @@ int alofdft_default_params(alofdft_params* p);
 
 /* Creates a context on HIP device `hip_device` that enqueues all work on
  * `hip_stream` (a hipStream_t, borrowed, may be NULL for the null stream).  The
- * context allocates its device workspace lazily and owns it until destroy. */
+ * context allocates its device workspace lazily and owns it until destroy.  With
+ * the environment variable ALOFDFT_PROGRESS set at creation, its solves write one
+ * line to stderr per 100 nonlinear-CG steps and per augmented-Lagrangian step. */
 int alofdft_create(alofdft_ctx** out, int hip_device, void* hip_stream);
 void alofdft_destroy(alofdft_ctx* ctx);
 

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <condition_variable>
 #include <deque>
@@ -41,6 +42,7 @@ struct alofdft_ctx {
   int variant = -1;       // stencil tile variant (-1: chosen per grid)
   int target_blocks = 0;  // 0: one round of resident workgroups
   int inner_tol_exp = 6;  // FP32 inner CG reduces the residual by 10^-inner_tol_exp
+  int progress = 0;       // ALOFDFT_PROGRESS set: one stderr line per 100 NLCG steps and per AL step
   int cg_schedule = 1;    // first half of each CG iteration: 0 stencil of p, 1 stencil of r (linearity)
   // geometry each padded work array was last zeroed for (its halo is zero only then)
   std::map<std::string, std::string> geom_key;
@@ -893,6 +895,8 @@ class Solver {
       restart = since_restart >= P_->restart_every || beta <= 0.0;
       if (restart) since_restart = 0;
       ++its;
+      if (c_->progress && its % 100 == 0)
+        std::fprintf(stderr, "alofdft: nlcg step %lld |g| %.3e cg %lld\n", its, gn, counts_.cg_iters);
     }
     gnorm = gn;
     return status;
@@ -925,6 +929,9 @@ class Solver {
       dE = q == 0 ? 0.0 : E - E_prev;
       E_prev = E;
       eta_star = eta - C / mu;  // Algorithm AugLag multiplier update
+      if (c_->progress)
+        std::fprintf(stderr, "alofdft: AL step %d E %.12f C_h/N %.3e nlcg %lld cg %lld\n", q + 1, E,
+                     std::fabs(C) / S_->N_elec, its, counts_.cg_iters);
       if (std::fabs(C) / S_->N_elec < P_->tol_constraint && st == 0) {
         status = ALOFDFT_OK;
         break;
@@ -1276,6 +1283,7 @@ int alofdft_create(alofdft_ctx** out, int hip_device, void* hip_stream) {
   if (!c) return ALOFDFT_OUT_OF_MEMORY;
   c->device = hip_device;
   c->stream = (hipStream_t)hip_stream;
+  c->progress = std::getenv("ALOFDFT_PROGRESS") != nullptr;
   int st = guarded(c, [&]() {
     HIPC(c, hipHostMalloc((void**)&c->pin, 4096, hipHostMallocDefault));
     HIPC(c, hipEventCreate(&c->ev0));

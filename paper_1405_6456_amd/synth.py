@@ -104,6 +104,31 @@ def initial_u(grid: Grid, N: float, seed: int = 6456, amp: float = 0.05) -> np.n
     return (math.sqrt(N / V) * (1.0 + amp * node_noise(seed, grid.npts))).reshape(grid.shape)
 
 
+def atomic_guess(system, width: float = 1.5, floor: float = 1e-3) -> np.ndarray:
+    """u0 = sqrt(rho0) for a superposition of one Gaussian of Z_J electrons per atom,
+    rho_J(r) = Z_J (pi w^2)^(-3/2) exp(-r^2/w^2) (cut at r = 5w), plus floor x N/V, scaled
+    so that h^3 sum rho0 = N: an initial guess of the atomic-density kind the paper uses
+    for its clusters, for systems where the uniform guess starts too far away."""
+    g = system.grid
+    h = g.h
+    rho = np.zeros(g.shape)
+    rc = 5.0 * width
+    norm = (math.pi * width * width) ** -1.5
+    axes = [g.origin[a] + h * np.arange(g.n[a]) for a in range(3)]
+    for J in range(system.M):
+        lo = [max(0, int(math.floor((system.R[J, a] - rc - g.origin[a]) / h))) for a in range(3)]
+        hi = [min(g.n[a] - 1, int(math.ceil((system.R[J, a] + rc - g.origin[a]) / h))) for a in range(3)]
+        if any(lo[a] > hi[a] for a in range(3)):
+            continue
+        d = [axes[a][lo[a]:hi[a] + 1] - system.R[J, a] for a in range(3)]
+        r2 = d[2][:, None, None] ** 2 + d[1][None, :, None] ** 2 + d[0][None, None, :] ** 2
+        rho[lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1] += system.Z[J] * norm * np.exp(-r2 / (width * width))
+    V = g.npts * h ** 3
+    rho += floor * system.N / V
+    rho *= system.N / (h ** 3 * rho.sum())
+    return np.sqrt(rho)
+
+
 def displacements(M: int, seed: int, magnitude: float = 0.1) -> np.ndarray:
     """Random displacement of exactly `magnitude` Bohr per atom, uniform direction.
 
