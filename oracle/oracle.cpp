@@ -625,38 +625,52 @@ static int nlcg(Work& W, double* u, double eta, double mu, OrEnergies* e_out, do
       slope0 = dot(N, g.data(), d.data());
     }
     std::copy(u, u + N, u_start.begin());
-    // line search on the directional derivative
-    double a = 0.0, b = INFINITY;
-    double t_prev = 0.0, s_prev = slope0;
+    // line search on the directional derivative from u_start along d; false when no
+    // finite point was found (the last trial overshot to a non-finite value)
     double t_cur = P->sigma0;
-    double s_cur = trial(t_cur);
-    // a trial with a non-finite slope or L overshot: it closes the bracket from above
+    double s_cur = 0.0;
     auto bad = [&]() { return !std::isfinite(s_cur) || !std::isfinite(e.L); };
-    if (s_cur > 0.0 || bad()) b = t_cur; else a = t_cur;
-    for (int j = 0; j < P->max_secant || bad(); ++j) {
-      if (bad()) {
-        if (j > 60) break;
-        t_prev = a;
-        s_prev = slope0;
-        t_cur = 0.5 * (a + b);
-        s_cur = trial(t_cur);
-        if (s_cur > 0.0 || bad()) b = t_cur; else a = t_cur;
-        continue;
-      }
-      if (std::fabs(s_cur) <= P->secant_rel * std::fabs(slope0)) break;
-      double curv = (s_cur - s_prev) / (t_cur - t_prev);
-      double t_new = (curv > 0.0) ? t_cur - s_cur / curv : NAN;
-      double hi = std::isfinite(b) ? b : 4.0 * std::max(a, t_cur);
-      if (!(t_new > a && t_new < hi)) t_new = std::isfinite(b) ? 0.5 * (a + b) : 2.0 * std::max(a, t_cur);
-      t_prev = t_cur;
-      s_prev = s_cur;
-      t_cur = t_new;
+    auto search = [&](double slope0) {
+      double a = 0.0, b = INFINITY;
+      double t_prev = 0.0, s_prev = slope0;
+      t_cur = P->sigma0;
       s_cur = trial(t_cur);
-      if (P->verbose > 2)
-        std::printf("      secant j=%d t=%.4e slope=%.4e slope0=%.4e [a=%.3e b=%.3e]\n", j, t_cur, s_cur, slope0, a, b);
-      if (s_cur > 0.0 || bad()) b = std::min(b, t_cur); else a = std::max(a, t_cur);
+      // a trial with a non-finite slope or L overshot: it closes the bracket from above
+      if (s_cur > 0.0 || bad()) b = t_cur; else a = t_cur;
+      for (int j = 0; j < P->max_secant || bad(); ++j) {
+        if (bad()) {
+          if (j > 60) break;
+          t_prev = a;
+          s_prev = slope0;
+          t_cur = 0.5 * (a + b);
+          s_cur = trial(t_cur);
+          if (s_cur > 0.0 || bad()) b = t_cur; else a = t_cur;
+          continue;
+        }
+        if (std::fabs(s_cur) <= P->secant_rel * std::fabs(slope0)) break;
+        double curv = (s_cur - s_prev) / (t_cur - t_prev);
+        double t_new = (curv > 0.0) ? t_cur - s_cur / curv : NAN;
+        double hi = std::isfinite(b) ? b : 4.0 * std::max(a, t_cur);
+        if (!(t_new > a && t_new < hi)) t_new = std::isfinite(b) ? 0.5 * (a + b) : 2.0 * std::max(a, t_cur);
+        t_prev = t_cur;
+        s_prev = s_cur;
+        t_cur = t_new;
+        s_cur = trial(t_cur);
+        if (P->verbose > 2)
+          std::printf("      secant j=%d t=%.4e slope=%.4e slope0=%.4e [a=%.3e b=%.3e]\n", j, t_cur, s_cur, slope0, a, b);
+        if (s_cur > 0.0 || bad()) b = std::min(b, t_cur); else a = std::max(a, t_cur);
+      }
+      return !bad();
+    };
+    bool ok = search(slope0);
+    if (!ok && since_restart > 0) {
+      // no finite point along the conjugate direction: search again from the same
+      // point along the preconditioned steepest-descent direction s
+      d = s;
+      since_restart = 0;
+      ok = search(-delta_new);
     }
-    if (bad()) {  // no finite point found along d
+    if (!ok) {  // no finite point found along d
       status = -4;
       break;
     }
@@ -668,7 +682,9 @@ static int nlcg(Work& W, double* u, double eta, double mu, OrEnergies* e_out, do
     delta_new = -dot(N, g.data(), s.data());
     double beta = (delta_new - delta_mid) / delta_old;
     ++since_restart;
-    if (since_restart >= P->restart_every || beta <= 0.0) {
+    // restart also when successive residuals have lost orthogonality (Powell's test,
+    // |r_new . s_old| >= 0.2 r_new . s_new), before the direction can run away
+    if (since_restart >= P->restart_every || beta <= 0.0 || std::fabs(delta_mid) >= 0.2 * delta_new) {
       d = s;
       since_restart = 0;
     } else {

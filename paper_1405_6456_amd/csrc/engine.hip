@@ -763,6 +763,9 @@ class Solver {
       // a non-finite charge: report the trial as non-finite; phi is reset to the
       // potential at the start of the line (or zero) so later solves start clean
       bad_ = true;
+      if (c_->progress)
+        std::fprintf(stderr, "alofdft: Poisson solve failed (non-finite or p.Ap <= 0) after %lld CG iterations\n",
+                     ps.iters);
       if (nh_ >= 1) {
         CombineOp cp{phi_, ph_[0], nullptr, nullptr, 1.0, 0.0, 0.0, nullptr};
         launch_pw(c_, g_, cp);
@@ -790,6 +793,13 @@ class Solver {
     counts_.matvec_fp64++;
     for (int i = 0; i < G_NRED; ++i)
       if (!std::isfinite(ev.gr[i])) bad_ = true;
+    if (bad_ && c_->progress) {
+      std::fprintf(stderr, "alofdft: non-finite residual sums:");
+      for (int i = 0; i < G_NRED; ++i) std::fprintf(stderr, " %.3e", ev.gr[i]);
+      std::fprintf(stderr, " | density sums:");
+      for (int i = 0; i < kUpdRed; ++i) std::fprintf(stderr, " %.3e", ev.upd[i]);
+      std::fprintf(stderr, "\n");
+    }
   }
 
   // Evaluation that must be finite (start point, new outer step, single evaluations).
@@ -881,7 +891,22 @@ class Solver {
         if (s_cur > 0.0 || bad_) b = std::min(b, t_cur); else a = std::max(a, t_cur);
       }
       if (bad_) {
-        set_err(c_, "no finite point along the search direction");
+        if (bet != 0.0) {
+          // no finite point along the conjugate direction: search again from the same
+          // point along s (v back to the start point, phi to its potential, the s
+          // buffers to their order before this line)
+          if (c_->progress) std::fprintf(stderr, "alofdft: NLCG step %lld: conjugate direction overflowed, restart\n", its);
+          CombineOp cv{v_, us_, nullptr, nullptr, 1.0, 0.0, 0.0, nullptr};
+          launch_pw(c_, g_, cv);
+          CombineOp cp{phi_, ph_[0], nullptr, nullptr, 1.0, 0.0, 0.0, nullptr};
+          launch_pw(c_, g_, cp);
+          std::swap(s_cur_, s_prev_);
+          restart = true;
+          since_restart = 0;
+          continue;
+        }
+        set_err(c_, "no finite point along the search direction (NLCG step %lld, last t %.3e, bracket [%.3e, %.3e])",
+                its, t_cur, a, b);
         throw Fail{ALOFDFT_NUMERICAL};
       }
       cur = ev;
@@ -892,7 +917,9 @@ class Solver {
       beta = (delta_new - delta_mid) / delta_old;
       gd_unsigned = cur.gr[G_GD];
       ++since_restart;
-      restart = since_restart >= P_->restart_every || beta <= 0.0;
+      // restart also when successive residuals have lost orthogonality (Powell's test,
+      // |r_new . s_old| >= 0.2 r_new . s_new), before the direction can run away
+      restart = since_restart >= P_->restart_every || beta <= 0.0 || std::fabs(delta_mid) >= 0.2 * delta_new;
       if (restart) since_restart = 0;
       ++its;
       if (c_->progress && its % 100 == 0)

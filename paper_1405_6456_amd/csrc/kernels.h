@@ -17,6 +17,8 @@
 
 #include <cmath>
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace alofdft {
@@ -27,6 +29,13 @@ __device__ inline double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   return v;
 }
+
+// Ops whose stencil input does not depend on the scalars their prologue computes
+// declare LATE_BEGIN = true.
+template <class Op, class = void>
+struct late_begin : std::false_type {};
+template <class Op>
+struct late_begin<Op, std::void_t<decltype(Op::LATE_BEGIN)>> : std::bool_constant<Op::LATE_BEGIN> {};
 
 // Reduces acc[0..NRED) over the block; thread r < NRED writes component r to out[r].
 template <int NRED, int NT>
@@ -289,7 +298,12 @@ __global__ void __launch_bounds__(64 * BY) k_stencil2(Geom g, StencilW<T> W, int
   __shared__ T lds[2][LY * LX];
 
   Op o = op;
-  if (!o.template begin<NT>()) return;
+  // an op whose loads do not depend on its prologue's scalars starts the queue
+  // loads first, so the prologue's reduction overlaps them
+  constexpr bool LATE = late_begin<Op>::value;
+  if constexpr (!LATE) {
+    if (!o.template begin<NT>()) return;
+  }
 
   const uint32_t nb = (uint32_t)(g.total * (long long)ES);
   const int ntile = tiles_x * tiles_y;
@@ -370,6 +384,9 @@ __global__ void __launch_bounds__(64 * BY) k_stencil2(Geom g, StencilW<T> W, int
     for (int i = 0; i < HR; ++i) hrg[i] = hok[i] ? o.loadb(nb, vl, so + hro[i] - rbias) : T(0);
 #pragma unroll
     for (int m = 0; m < XH; ++m) xrg[m] = xok[m] ? o.loadb(nb, xo[m], so - xbias) : T(0);
+  }
+  if constexpr (LATE) {
+    if (!o.template begin<NT>()) return;
   }
 
   for (int t0 = 0; t0 < len; t0 += K) {
@@ -770,6 +787,7 @@ struct CGP1Op {
 template <typename T>
 struct CGP1LOp : CGP1Op<T> {
   static constexpr bool NEEDC = true;
+  static constexpr bool LATE_BEGIN = true;  // the stencil input r needs no scalar
   using CGP1Op<T>::r;
   using CGP1Op<T>::pnew;
   using CGP1Op<T>::Ap;
@@ -831,11 +849,12 @@ struct CGP2Op {
 
 // Second half of a CG iteration (CGP2Op) with one grid row per wave: each lane
 // issues the loads of all its nodes of the row (up to 4 x 64 per pass) before any
-// store, so a row costs one memory latency.
+// store, so a row costs one memory latency.  The first row's loads go out before
+// the prologue that reduces p.Ap (they do not depend on alpha), so the two
+// latencies overlap.
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT) k_cg_update(Geom g, CGP2Op<T> op) {
   CGP2Op<T> o = op;
-  if (!o.template begin<NT>()) return;
   double red[1] = {0.0};
   const int lane = threadIdx.x & 63;
   const int nwaves = gridDim.x * (NT / 64);
@@ -844,22 +863,31 @@ __global__ void __launch_bounds__(NT) k_cg_update(Geom g, CGP2Op<T> op) {
   T* __restrict__ r = o.r;
   const T* __restrict__ p = o.p;
   const T* __restrict__ Ap = o.Ap;
-  const T alpha = o.alpha;
-  for (int row = blockIdx.x * (NT / 64) + (threadIdx.x >> 6); row < nrows; row += nwaves) {
-    const int j = row % g.ny, k = row / g.ny;
-    const long long rb = g.base + (long long)k * g.plane + (long long)j * g.px;
-    for (int i0 = 0; i0 < g.nx; i0 += 4 * 64) {
-      T xv[4], pv[4], rv[4], av[4];
+  T xv[4], pv[4], rv[4], av[4];
+  auto load = [&](long long rb, int i0) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int i = i0 + lane + 64 * u;
-        if (i < g.nx) {
-          xv[u] = x[rb + i];
-          pv[u] = p[rb + i];
-          rv[u] = r[rb + i];
-          av[u] = Ap[rb + i];
-        }
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + lane + 64 * u;
+      if (i < g.nx) {
+        xv[u] = x[rb + i];
+        pv[u] = p[rb + i];
+        rv[u] = r[rb + i];
+        av[u] = Ap[rb + i];
       }
+    }
+  };
+  auto rowbase = [&](int row) {
+    const int j = row % g.ny, k = row / g.ny;
+    return g.base + (long long)k * g.plane + (long long)j * g.px;
+  };
+  const int row0 = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  if (row0 < nrows) load(rowbase(row0), 0);
+  if (!o.template begin<NT>()) return;
+  const T alpha = o.alpha;
+  for (int row = row0; row < nrows; row += nwaves) {
+    const long long rb = rowbase(row);
+    for (int i0 = 0; i0 < g.nx; i0 += 4 * 64) {
+      if (row != row0 || i0 != 0) load(rb, i0);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int i = i0 + lane + 64 * u;
@@ -940,7 +968,7 @@ struct DirOp {
   __device__ void apply(long long i, int ii, int jj, int kk, double* red) const {
     const double u = fabs(v[i]);
     us[i] = u;
-    const double dn = s[i] + beta * d[i];
+    const double dn = beta != 0.0 ? s[i] + beta * d[i] : s[i];  // a restart never reads the old d
     d[i] = dn;
     const double vi = u + t * dn;
     v[i] = vi;
