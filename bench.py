@@ -38,11 +38,17 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="fcc2", choices=["single", "fcc2", "fcc5", "fcc10"])
-    ap.add_argument("--precision", default="fp32r", choices=["fp32r", "fp64"])
-    ap.add_argument("--no-fp64-ref", action="store_true", help="skip the FP64 comparison solve")
+    ap.add_argument("--precision", default="auto", choices=["auto", "fp32r", "fp64"],
+                    help="auto: FP64 on grids up to 1.5e6 nodes (the single atom, fcc2, fcc5), "
+                         "FP32 CG inside FP64 refinement above (fcc10)")
+    ap.add_argument("--no-fp64-ref", action="store_true", help="skip the solve in the other precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
-    ap.add_argument("--sample-every", type=int, default=8, help="CG kernel launches per timed sample")
+    ap.add_argument("--sample-every", type=int, default=64,
+                    help="CG kernel launches per timed sample (an event-stamped launch costs a few us more)")
+    ap.add_argument("--cg-schedule", type=int, default=-1, choices=[-1, 0, 1, 2],
+                    help="CG launches per iteration: 0/1 two launches, 2 pipelined (one launch, FP64 only), "
+                         "-1 the library's automatic choice")
     ap.add_argument("--mode", default="solve", choices=["solve", "stencil", "counters", "serve"],
                     help="stencil: only the streaming stencil measurement; counters: a short refined "
                          "Poisson solve and a reference copy (for counter passes); serve: the request "
@@ -100,7 +106,8 @@ def summarize_counters(fetch_csv, write_csv, key):
     res = {}
     for path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
         pk = per_kernel(path, counter)
-        cg = [v for k, vs in pk.items() if "CGP1LOp<float>" in k and "k_stencil" in k for v in vs]
+        name = "CGPipeOp<double>" if key.startswith("cgpipe") else "CGP1LOp<float>"
+        cg = [v for k, vs in pk.items() if name in k and "k_stencil" in k for v in vs]
         cp = [v for k, vs in pk.items() if "elementwise" in k or "copy" in k.lower() for v in vs]
         cp = [v for v in cp if v > 0.5 * max(cp)] if cp else []
         if not cg or not cp:
@@ -255,20 +262,25 @@ def serve(args):
     print(json.dumps(line), flush=True)
 
 
-def counters_mode(S):
-    """A short refined Poisson solve on the workload grid (the FP32 CG stencil pass is the
-    kernel of interest), then a 256 MiB reference copy whose counter readings scale the
-    byte counters."""
+def counters_mode(S, schedule, precision):
+    """A short Poisson solve on the workload grid in the bench's precision for it (its CG
+    kernel is the one of interest), then a 256 MiB reference copy whose counter readings
+    scale the byte counters."""
     import torch
 
     import paper_1405_6456_amd as lib
     from paper_1405_6456_amd import synth
 
     ctx = lib.Context(0)
+    ctx.set_cg_schedule(schedule)
     u0 = synth.initial_u(S.grid, S.N)
     b, _ = ctx.pseudocharge(S)
     rho = (torch.from_numpy(u0 * u0).to("cuda:0") + b).contiguous()
-    _, its, rel = ctx.poisson(rho, S.grid, precision=lib.FP32_REFINED, tol=1e-10, max_cg=200)
+    if precision == "auto":
+        prec = lib.FP32_REFINED if S.grid.npts > 1_500_000 else lib.FP64
+    else:
+        prec = lib.FP32_REFINED if precision == "fp32r" else lib.FP64
+    _, its, rel = ctx.poisson(rho, S.grid, precision=prec, tol=1e-10, max_cg=200)
     torch.cuda.synchronize()
     src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
     dst = torch.empty_like(src)
@@ -298,7 +310,7 @@ def main():
         return serve(args)
     S = synth.config(args.workload)
     if args.mode == "counters":
-        return counters_mode(S)
+        return counters_mode(S, args.cg_schedule, args.precision)
     if args.mode == "stencil":
         ctx = lib.Context(0)
         for dt in (0, 1):
@@ -320,9 +332,15 @@ def main():
     # uniform guess stalls the 4000-atom cluster far from the minimiser); the single atom
     # from the seeded uniform guess of its configuration
     u0 = synth.initial_u(S.grid, S.N) if args.workload == "single" else synth.atomic_guess(S)
-    prec = lib.FP32_REFINED if args.precision == "fp32r" else lib.FP64
+    if args.precision == "auto":
+        # FP32 pays only where the CG iterations are bandwidth bound; below, the FP64 path
+        # (pipelined CG) is faster, and it is what the smaller workloads are specified in
+        prec = lib.FP32_REFINED if S.grid.npts > 1_500_000 else lib.FP64
+    else:
+        prec = lib.FP32_REFINED if args.precision == "fp32r" else lib.FP64
     prm = lib.default_params(precision=prec)
     ctx = lib.Context(0)
+    ctx.set_cg_schedule(args.cg_schedule)
     npts = S.grid.npts
     # the initial guess is resident in HBM before the timed region (only the atom list and
     # the 3M forces cross PCIe inside a solve)
@@ -338,7 +356,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     dt_idx = 1 if prec == lib.FP32_REFINED else 0
-    launches, mean_ms, kpts = ctx.cg_kernel_stats(dt_idx)
+    launches, mean_ms, kpts, sched = ctx.cg_kernel_stats(dt_idx)
     ctx.profile_cg_kernel(0)
 
     last = outs[-1]
@@ -346,15 +364,29 @@ def main():
     ms_per_step = 1e3 * wall / args.steps
     value = mv * npts / wall / 1e9
     esize = 4 if prec == lib.FP32_REFINED else 8
-    # algorithmic bytes of the CG stencil kernel per node: read r (stencil input), p and
-    # A p; write p and A p (the first half of each iteration, by linearity)
-    alg_bytes = 5 * esize * kpts
+    tag = 'f32' if esize == 4 else 'f64'
+    if sched == 2:
+        # algorithmic bytes of the pipelined CG iteration per node: read w (stencil input),
+        # z, s, p, x, r; write z, s, p, x, r and the next w
+        alg_bytes = 12 * esize * kpts
+        kernel_key = f"cgpipe_stencil_{tag}_{args.workload}"
+        kernel = ("CG iteration, pipelined (m = A w; z = m + beta z, s = w + beta s, p = r + beta p, "
+                  "x += alpha p, r -= alpha s, w -= alpha z; r.r, w.r): k_stencil2 CGPipeOp")
+    elif sched == 0:
+        # read r and p (stencil input p = r + beta p), write p and A p
+        alg_bytes = 4 * esize * kpts
+        kernel_key = f"cgp_stencil_{tag}_{args.workload}"
+        kernel = "CG first half (p = r + beta p, A p, p.Ap): k_stencil2 CGP1Op"
+    else:
+        # algorithmic bytes of the CG stencil kernel per node: read r (stencil input), p and
+        # A p; write p and A p (the first half of each iteration, by linearity)
+        alg_bytes = 5 * esize * kpts
+        kernel_key = f"cg_stencil_{tag}_{args.workload}"
+        kernel = "CG first half (A r; p = r + beta p, A p = A r + beta A p; p.Ap): k_stencil2 CGP1LOp"
     achieved = alg_bytes / (mean_ms * 1e-3) / 1e9 if mean_ms > 0 else 0.0
-    kernel_key = f"cg_stencil_{'f32' if esize == 4 else 'f64'}_{args.workload}"
     tr = traffic_for(kernel_key)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
-                "kernel": "CG first half (A r; p = r + beta p, A p = A r + beta A p; p.Ap): k_stencil2 CGP1LOp",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr, "kernel": kernel,
                 "alg_bytes_per_launch": alg_bytes, "mean_launch_ms": round(mean_ms, 5), "timed_launches": launches}
 
     # streaming stencil throughput (six rotating buffer pairs, more than the 256 MB cache)
@@ -372,15 +404,25 @@ def main():
                              "hbm_frac": round(nbig * 2 * es / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     extra = {}
-    if not args.no_fp64_ref and prec == lib.FP32_REFINED:
+    if not args.no_fp64_ref:
+        # the same solve in the other precision: the FP32-refined path's speedup over the
+        # FP64 GPU path and its error against it, whichever of the two is timed above
+        other = lib.FP64 if prec == lib.FP32_REFINED else lib.FP32_REFINED
         t = time.perf_counter()
-        ref = ctx.solve_device(S, lib.default_params(precision=lib.FP64), u0_dev, want_forces=True)
-        t64 = time.perf_counter() - t
-        extra["fp64_path"] = {"ms_per_solve": round(1e3 * t64, 1), "status": ref["status"],
-                              "cg_iters": ref["cg_iters"], "E_total": ref["E_total"]}
-        extra["speedup_vs_fp64"] = round(t64 / (wall / args.steps), 3)
-        extra["err_vs_fp64"] = {"E_per_atom": abs(last["E_total"] - ref["E_total"]) / S.M,
-                                "F_max": float(np.abs(last["forces"] - ref["forces"]).max())}
+        oth = ctx.solve_device(S, lib.default_params(precision=other), u0_dev, want_forces=True)
+        t_oth = time.perf_counter() - t
+        t_main = wall / args.steps
+        entry = {"ms_per_solve": round(1e3 * t_oth, 1), "status": oth["status"], "cg_iters": oth["cg_iters"],
+                 "E_total": oth["E_total"]}
+        if prec == lib.FP32_REFINED:
+            extra["fp64_path"] = entry
+            t32, t64, r32, r64 = t_main, t_oth, last, oth
+        else:
+            extra["fp32r_path"] = entry
+            t32, t64, r32, r64 = t_oth, t_main, oth, last
+        extra["speedup_fp32r_vs_fp64"] = round(t64 / t32, 3)
+        extra["err_fp32r_vs_fp64"] = {"E_per_atom": abs(r32["E_total"] - r64["E_total"]) / S.M,
+                                      "F_max": float(np.abs(r32["forces"] - r64["forces"]).max())}
 
     cpu = None
     if not args.no_cpu_baseline:

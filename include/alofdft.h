@@ -236,20 +236,33 @@ int alofdft_bench_stencil(alofdft_ctx* ctx, const int n[3], int fd_half_width, i
 int alofdft_set_tuning(alofdft_ctx* ctx, int stencil_variant, int target_blocks, int inner_tol_exp);
 
 /* Schedule of the conjugate-gradient iterations of every Poisson solve of the
- * context (Sec. 4: the discrete Poisson problem solved by CG).  Each iteration is
- * two launches; the second is x += alpha p, r -= alpha A p and r.r.  The first:
+ * context (Sec. 4: the discrete Poisson problem solved by CG).  Schedules 0 and 1
+ * take two launches per iteration; the second is x += alpha p, r -= alpha A p and
+ * r.r.  The first:
  *   0  p = r + beta p formed on load (the stencil input is r and p over every
  *      tile's halo), A p by the stencil, p.Ap;
- *   1  (default) A r by the stencil (one input array), then p = r + beta p and
+ *   1  A r by the stencil (one input array), then p = r + beta p and
  *      A p = A r + beta A p updated in place at each node, p.Ap.
- * Both stop on the same relative residual of r; their iterates differ by rounding.
+ *   2  one launch and one reduction per iteration, pipelined form (Chronopoulos-
+ *      Gear scalars, Ghysels-Vanroose recurrences): w = A r, s = A p and z = A s
+ *      are kept as vectors, the stencil is applied to the stored w (m = A w), then
+ *      z = m + beta z, s = w + beta s, p = r + beta p, x += alpha p, r -= alpha s,
+ *      w -= alpha z, with r.r and w.r reduced together; alpha = r.r / (w.r -
+ *      beta r.r / alpha_prev).  FP64 solves only (the FP32 inner solves of the
+ *      refined path use 1: in FP32 these recurrences stall near 1e-4).  r is a
+ *      recurrence here, so a converged solve is restarted once from its true
+ *      residual, which stops at once when the tolerance holds.
+ *  -1  (default) automatic: 2 for FP64 solves on grids of at most 1.5e6 nodes
+ *      (latency-bound iterations, where one launch instead of two pays), else 1.
+ * All stop on the same relative residual; their iterates differ by rounding.
  * INVALID_ARGUMENT for a null context or another value. */
 int alofdft_set_cg_schedule(alofdft_ctx* ctx, int schedule);
 
 /* Measurement of the dominant kernel.  With sample_every > 0, every
  * sample_every-th launch of the conjugate-gradient stencil kernel (the fused
- * first launch of each CG iteration: A r, p, A p and p.Ap with schedule 1, the
- * default; p = r + beta p, A p and p.Ap with schedule 0) carries a pair of HIP
+ * first launch of each CG iteration: A r, p, A p and p.Ap with schedule 1;
+ * p = r + beta p, A p and p.Ap with schedule 0; the whole iteration with
+ * schedule 2) carries a pair of HIP
  * events that the runtime stamps with the start and end of the kernel itself
  * (hipExtLaunchKernel), so the mean is the kernel duration a kernel trace reports;
  * launches made after a solve has converged (which exit at once) are not counted.  sample_every = 0 stops sampling.  Calling it
@@ -257,9 +270,12 @@ int alofdft_set_cg_schedule(alofdft_ctx* ctx, int schedule);
 int alofdft_profile_cg_kernel(alofdft_ctx* ctx, int sample_every);
 
 /* Statistics of the sampled launches for dtype 0 (FP64 CG) or 1 (FP32 inner CG of
- * the refined solve): number of timed launches, mean duration in ms, and the grid
- * points (n[0]*n[1]*n[2]) of the last timed launch.  All three pointers required. */
-int alofdft_cg_kernel_stats(alofdft_ctx* ctx, int dtype, long long* launches, double* mean_ms, long long* points);
+ * the refined solve): number of timed launches, mean duration in ms, the grid
+ * points (n[0]*n[1]*n[2]) of the last timed launch and, if schedule is not null,
+ * the CG schedule (0..2, see alofdft_set_cg_schedule) those launches ran, -1 if
+ * none.  The first three pointers required. */
+int alofdft_cg_kernel_stats(alofdft_ctx* ctx, int dtype, long long* launches, double* mean_ms, long long* points,
+                            int* schedule);
 
 /* ------------------------------------------------------------------ serving
  * A request loop that solves independent ground-state requests (systems of any

@@ -111,7 +111,8 @@ def lib():
         L.alofdft_server_destroy.argtypes = [_VP]
         L.alofdft_server_destroy.restype = None
         L.alofdft_profile_cg_kernel.argtypes = [_VP, C.c_int]
-        L.alofdft_cg_kernel_stats.argtypes = [_VP, C.c_int, C.POINTER(C.c_longlong), _DP, C.POINTER(C.c_longlong)]
+        L.alofdft_cg_kernel_stats.argtypes = [_VP, C.c_int, C.POINTER(C.c_longlong), _DP, C.POINTER(C.c_longlong),
+                                              C.POINTER(C.c_int)]
         _lib = L
     return _lib
 
@@ -188,9 +189,12 @@ class Context:
         _check(self, lib().alofdft_set_tuning(self.handle, variant, target_blocks, inner_tol_exp))
 
     # ------------------------------------------------------------- full solve
-    def set_cg_schedule(self, schedule=1):
-        """First half of each CG iteration: 0 applies the stencil to p = r + beta p;
-        1 (default) applies it to r and forms A p = A r + beta A p by linearity."""
+    def set_cg_schedule(self, schedule=-1):
+        """CG launches per iteration: 0 applies the stencil to p = r + beta p, then
+        updates x and r; 1 applies it to r and forms A p = A r + beta A p by linearity,
+        then updates x and r; 2 (FP64 solves only) fuses the iteration into one launch
+        with one reduction in the pipelined form, the stencil applied to the stored
+        w = A r; -1 (default) picks 2 for FP64 solves on grids up to 1.5e6 nodes, else 1."""
         _check(self, lib().alofdft_set_cg_schedule(self.handle, int(schedule)))
 
     def solve(self, system, params: Params | None = None, u0=None, want_fields=True, want_forces=True):
@@ -294,10 +298,12 @@ class Context:
         _check(self, lib().alofdft_profile_cg_kernel(self.handle, int(sample_every)))
 
     def cg_kernel_stats(self, dtype=0):
-        """(timed launches, mean ms per launch, grid points per launch) for dtype 0 (FP64) / 1 (FP32)."""
-        n, ms, pts = C.c_longlong(), C.c_double(), C.c_longlong()
-        _check(self, lib().alofdft_cg_kernel_stats(self.handle, dtype, C.byref(n), C.byref(ms), C.byref(pts)))
-        return n.value, ms.value, pts.value
+        """(timed launches, mean ms per launch, grid points per launch, CG schedule of those
+        launches or -1) for dtype 0 (FP64) / 1 (FP32)."""
+        n, ms, pts, sch = C.c_longlong(), C.c_double(), C.c_longlong(), C.c_int()
+        _check(self, lib().alofdft_cg_kernel_stats(self.handle, dtype, C.byref(n), C.byref(ms), C.byref(pts),
+                                                   C.byref(sch)))
+        return n.value, ms.value, pts.value, sch.value
 
     def bench_stencil(self, n, fd_half_width=6, dtype=0, reps=100, nbuf=6):
         """Mean kernel time (ms) of one stencil application over a rotation of nbuf buffer pairs."""

@@ -38,8 +38,9 @@ struct CGState {
   double rhs2;     // ||rhs||^2
   double thresh;   // tol^2 ||rhs||^2
   double rr_last;  // r.r when the solve stopped
+  double ah[2];    // alpha of iteration k, indexed by k & 1 (one-reduction schedule)
   long long iter;  // iterations completed
-  int done;        // 0 running, 1 converged, 2 non-finite
+  int done;        // 0 running, 1 converged, 2 non-finite, 3 zero rhs, 4 rounding breakdown
   int pad;
 };
 

@@ -43,7 +43,8 @@ struct alofdft_ctx {
   int target_blocks = 0;  // 0: one round of resident workgroups
   int inner_tol_exp = 6;  // FP32 inner CG reduces the residual by 10^-inner_tol_exp
   int progress = 0;       // ALOFDFT_PROGRESS set: one stderr line per 100 NLCG steps and per AL step
-  int cg_schedule = 1;    // first half of each CG iteration: 0 stencil of p, 1 stencil of r (linearity)
+  int cg_schedule = -1;   // CG launches: 0 stencil of p + update, 1 stencil of r (linearity) + update,
+                          // 2 pipelined (one launch, one reduction); -1 automatic (cg_schedule_for)
   // geometry each padded work array was last zeroed for (its halo is zero only then)
   std::map<std::string, std::string> geom_key;
   // sampled event timing of the CG stencil kernel (index 0: FP64, 1: FP32)
@@ -52,6 +53,7 @@ struct alofdft_ctx {
   long long prof_count[2] = {0, 0};
   double prof_ms[2] = {0.0, 0.0};
   long long prof_points[2] = {0, 0};
+  int prof_sched[2] = {-1, -1};  // CG schedule of the timed launches
 };
 
 namespace {
@@ -298,7 +300,149 @@ struct CGResult {
   long long iters = 0;
   double relres = 0.0;
   int done = 0;
+  int extra_mv = 0;  // stencil applications beyond one per iteration and the initial residual
 };
+
+// Largest grid (nodes) on which the automatic schedule runs FP64 solves pipelined: the
+// fused launch saves a launch and a reduction per iteration, which pays while the
+// iteration is latency bound; above it the extra bytes (12 arrays per node against
+// 11 for the two launches) cost more.
+constexpr long long kPipeMaxNodes = 1500000;
+
+// CG schedule of a solve: the context's choice, the automatic one for -1; FP32 solves
+// never run pipelined (its recurrences for w and r lose accuracy near 1e-4 in FP32).
+int cg_schedule_for(const alofdft_ctx* c, const Geom& g, bool fp64) {
+  int s = c->cg_schedule;
+  if (s < 0) s = (fp64 && (long long)g.nx * g.ny * g.nz <= kPipeMaxNodes) ? 2 : 1;
+  if (s == 2 && !fp64) s = 1;
+  return s;
+}
+
+// Whether CG launch k carries timing events: every prof_every-th launch, offset from
+// the host's polls of the solve state (every check_every launches), after which the
+// device has drained and the next launch starts cold.
+bool sampled(const alofdft_ctx* c, long long k) {
+  if (c->prof_every <= 0) return false;
+  const long long off = c->prof_every > 8 ? 5 : 0;
+  return k % c->prof_every == off;
+}
+
+// Kernel-stamped event pair number `used` of the context's pool (created on demand).
+std::pair<hipEvent_t, hipEvent_t> prof_pair(alofdft_ctx* c, size_t used) {
+  if (used == c->prof_pool.size()) {
+    hipEvent_t a, b;
+    HIPC(c, hipEventCreate(&a));
+    HIPC(c, hipEventCreate(&b));
+    c->prof_pool.push_back({a, b});
+  }
+  return c->prof_pool[used];
+}
+
+// The same CG in the pipelined form (one launch and one reduction per iteration,
+// CGPipeOp), after the residual of the guess and w = A r (CGWInitOp).  Same
+// arguments, stopping tests and result as cg_solve, plus verdict 4 (rounding breakdown).
+template <typename T>
+CGResult cg_solve_pipe(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* rhs, T* x, double tol,
+                       long long max_it, int check_every, const char* tag, bool init, const double* init_parts,
+                       int init_nparts, bool stop_on_stagnation) {
+  const std::string t(tag);
+  T* r = gridbuf<T>(c, t + ".r", g);
+  T* wv[2] = {gridbuf<T>(c, t + ".w0", g), gridbuf<T>(c, t + ".w1", g)};
+  T* sv = gridbuf<T>(c, t + ".Ap", g);
+  T* z = gridbuf<T>(c, t + ".z", g);
+  T* p = gridbuf<T>(c, t + ".p0", g);
+  const int maxsb = max_stencil_blocks(g, c->target_blocks);
+  double* partsI = bufT<double>(c, t + ".partsI", (size_t)std::max(maxsb, kPointwiseBlocks) * 2);
+  double* pp[2] = {bufT<double>(c, t + ".partsC", (size_t)maxsb * 2), bufT<double>(c, t + ".partsD", (size_t)maxsb * 2)};
+  CGState* st = bufT<CGState>(c, t + ".state", 1);
+  HIPC(c, hipMemsetAsync(st, 0, sizeof(CGState), c->stream));
+  const double* prev = init_parts;
+  int nprev = init_nparts;
+  if (init) {
+    CGInitOp<T> op{x, rhs, r, nullptr, partsI};
+    nprev = launch_stencil(c, g, A, op);
+    prev = partsI;
+  }
+  const double tol2 = tol * tol;
+  {
+    CGWInitOp<T> op{r, wv[0], sv, p, z, st, prev, nprev, tol2, pp[0]};
+    nprev = launch_stencil(c, g, A, op);
+    prev = pp[0];
+  }
+  const int pi = sizeof(T) == 8 ? 0 : 1;
+  std::vector<std::pair<long long, size_t>> pending;
+  size_t pool_used = 0;
+  auto harvest = [&](long long stop_iter) {
+    for (auto& pe : pending) {
+      if (pe.first >= stop_iter) continue;
+      float ms = 0.f;
+      HIPC(c, hipEventElapsedTime(&ms, c->prof_pool[pe.second].first, c->prof_pool[pe.second].second));
+      c->prof_ms[pi] += ms;
+      c->prof_count[pi]++;
+      c->prof_points[pi] = (long long)g.nx * g.ny * g.nz;
+      c->prof_sched[pi] = 2;
+    }
+    pending.clear();
+    pool_used = 0;
+  };
+  // iterate k reads the partials of the previous pass (pp[k & 1]) and writes pp[(k+1) & 1]
+  auto launch_k = [&](long long k, int last, hipEvent_t e0, hipEvent_t e1) {
+    const int a = (int)(k & 1), b = a ^ 1;
+    const CGPipeOp<T> op{wv[a], wv[b], r, sv, z, p, x, st, prev, nprev, (int)k, last, pp[b], T(0), T(0)};
+    nprev = launch_stencil(c, g, A, op, e0, e1);  // events stamp the kernel itself
+    prev = pp[b];
+  };
+  long long k = 0;
+  double best_rr = HUGE_VAL;
+  long long best_k = 0;
+  for (;; ++k) {
+    if (k >= max_it) break;
+    const bool timed = sampled(c, k);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) std::tie(e0, e1) = prof_pair(c, pool_used);
+    launch_k(k, 0, e0, e1);
+    if (timed) pending.push_back({k, pool_used++});
+    if ((k + 1) % check_every == 0) {
+      HIPC(c, hipMemcpyAsync(c->pin, st, sizeof(CGState), hipMemcpyDeviceToHost, c->stream));
+      sync(c);
+      const CGState* sp = (CGState*)c->pin;
+      harvest(sp->done ? sp->iter : k + 1);
+      if (sp->done) break;
+      if (stop_on_stagnation) {
+        const double rr = sp->rrh[sp->iter & 1];
+        if (rr < 0.5 * best_rr) {
+          best_rr = rr;
+          best_k = k;
+        } else if (k - best_k >= 256) {
+          ++k;
+          break;
+        }
+      }
+    }
+  }
+  HIPC(c, hipMemcpyAsync(c->pin, st, sizeof(CGState), hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  CGState s = *(CGState*)c->pin;
+  harvest(s.done ? s.iter : k);
+  if (!s.done) {
+    // verdict on the last residual without another update
+    launch_k(k, 1, nullptr, nullptr);
+    HIPC(c, hipMemcpyAsync(c->pin, st, sizeof(CGState), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    s = *(CGState*)c->pin;
+  }
+  CGResult res;
+  res.done = s.done;
+  res.extra_mv = 1;
+  if (s.done == 3) {
+    fill<T>(c, x, g.total, T(0));
+    return res;
+  }
+  res.iters = s.iter;
+  const double rr = s.done ? s.rr_last : s.rrh[s.iter & 1];
+  res.relres = s.rhs2 > 0 ? std::sqrt(rr / s.rhs2) : 0.0;
+  return res;
+}
 
 // CG on A x = rhs (A = -(1/4 pi) Delta_h, zero ghosts) from the guess in x, to
 // r.r <= tol^2 ||rhs||^2 (init = true: the residual is formed here; otherwise r,
@@ -307,10 +451,14 @@ template <typename T>
 CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* rhs, T* x, double tol, long long max_it,
                   int check_every, const char* tag, bool init = true, const double* init_parts = nullptr,
                   int init_nparts = 0, bool stop_on_stagnation = false) {
+  const int sched = cg_schedule_for(c, g, sizeof(T) == 8);
+  if (sched == 2)
+    return cg_solve_pipe<T>(c, g, A, rhs, x, tol, max_it, check_every, tag, init, init_parts, init_nparts,
+                            stop_on_stagnation);
   const std::string t(tag);
   T* r = gridbuf<T>(c, t + ".r", g);
   T* p0 = gridbuf<T>(c, t + ".p0", g);
-  T* p1 = gridbuf<T>(c, t + ".p1", g);
+  T* p1 = sched == 0 ? gridbuf<T>(c, t + ".p1", g) : p0;
   T* Ap = gridbuf<T>(c, t + ".Ap", g);
   const int maxsb = max_stencil_blocks(g, c->target_blocks);
   double* partsI = bufT<double>(c, t + ".partsI", (size_t)std::max(maxsb, kPointwiseBlocks) * 2);
@@ -343,6 +491,7 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
       c->prof_ms[pi] += ms;
       c->prof_count[pi]++;
       c->prof_points[pi] = (long long)g.nx * g.ny * g.nz;
+      c->prof_sched[pi] = sched;
     }
     pending.clear();
     pool_used = 0;
@@ -355,8 +504,8 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
     T* pold = (k & 1) ? p1 : p0;
     T* pnew = (k & 1) ? p0 : p1;
     CGP1Op<T> op1{r, pold, pnew, Ap, st, prev, nprev, nred_prev, (int)k, tol2, partsA, T(0)};
-    if (c->cg_schedule == 1) op1.pold = op1.pnew = p0;  // p and A p updated in place
-    const bool timed = c->prof_every > 0 && k % c->prof_every == 0;
+    if (sched == 1) op1.pold = op1.pnew = p0;  // p and A p updated in place
+    const bool timed = sampled(c, k);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
       if (pool_used == c->prof_pool.size()) {
@@ -368,7 +517,7 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
       e0 = c->prof_pool[pool_used].first;
       e1 = c->prof_pool[pool_used].second;
     }
-    const int nb1 = c->cg_schedule == 1 ? launch_stencil(c, g, A, CGP1LOp<T>{op1}, e0, e1)
+    const int nb1 = sched == 1 ? launch_stencil(c, g, A, CGP1LOp<T>{op1}, e0, e1)
                                         : launch_stencil(c, g, A, op1, e0, e1);  // events stamp the kernel itself
     if (timed) pending.push_back({k, pool_used++});
     CGP2Op<T> op2{x, r, op1.pnew, Ap, st, partsA, nb1, (int)k, partsB, T(0)};
@@ -403,7 +552,7 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
     T* pold = (k & 1) ? p1 : p0;
     T* pnew = (k & 1) ? p0 : p1;
     CGP1Op<T> op1{r, pold, pnew, Ap, st, prev, nprev, nred_prev, (int)k, tol2, partsA, T(0)};
-    if (c->cg_schedule == 1) {
+    if (sched == 1) {
       op1.pold = op1.pnew = p0;
       launch_stencil(c, g, A, CGP1LOp<T>{op1});
     } else {
@@ -438,11 +587,21 @@ PoissonStats poisson(alofdft_ctx* c, const Geom& g, int fdn, double h, int preci
   PoissonStats ps;
   const StencilW<double> A64 = stencil_weights<double>(fdn, h, -0.25 / M_PI);
   if (precision == ALOFDFT_FP64) {
-    CGResult r = cg_solve<double>(c, g, A64, rhs, x, tol, max_cg, check_every, "cg64");
-    ps.iters = r.iters;
-    ps.mv64 = r.iters + 1;
-    ps.relres = r.relres;
-    ps.status = r.done == 2 ? ALOFDFT_NUMERICAL : (r.done ? 0 : ALOFDFT_NOT_CONVERGED);
+    // the pipelined recurrences carry r rather than recompute it, so their verdict is
+    // checked once more from the true residual (a restart that stops at once when it
+    // holds); a rounding breakdown (verdict 4) also restarts from the current iterate
+    const bool pipe = cg_schedule_for(c, g, true) == 2;
+    for (int restart = 0; restart < 8; ++restart) {
+      CGResult r = cg_solve<double>(c, g, A64, rhs, x, tol, max_cg - ps.iters, check_every, "cg64");
+      ps.iters += r.iters;
+      ps.mv64 += r.iters + 1 + r.extra_mv;
+      ps.relres = r.relres;
+      const bool again = pipe && ((r.done == 1 && r.iters > 0) || r.done == 4);
+      if (again && ps.iters < max_cg && restart < 7) continue;
+      ps.status = r.done == 2 ? ALOFDFT_NUMERICAL : (r.done == 1 || r.done == 3 ? 0 : ALOFDFT_NOT_CONVERGED);
+      return ps;
+    }
+    ps.status = ALOFDFT_NOT_CONVERGED;
     return ps;
   }
   const StencilW<float> A32 = stencil_weights<float>(fdn, h, -0.25 / M_PI);
@@ -484,7 +643,7 @@ PoissonStats poisson(alofdft_ctx* c, const Geom& g, int fdn, double h, int preci
     CGResult ir = cg_solve<float>(c, g, A32, nullptr, x32, want, max_cg - ps.iters, check_every, "cg32", false,
                                   partsF, nbf, true);
     ps.iters += ir.iters;
-    ps.mv32 += ir.iters;
+    ps.mv32 += ir.iters + ir.extra_mv;
     if (ir.done == 2) { ps.status = ALOFDFT_NUMERICAL; return ps; }
     AddFloatOp add{x, x32, nullptr};
     launch_pw(c, g, add);
@@ -1132,8 +1291,9 @@ size_t footprint(const alofdft_system* s, const alofdft_params* p) {
   const Geom g = make_geom(s->n, p->fd_half_width);
   const size_t T = (size_t)g.total;
   const size_t n = (size_t)s->n[0] * s->n[1] * s->n[2];
-  // solver arrays (12), FP64 CG (4), refinement residual (1): double; FP32 CG (4) + correction (1): float
-  const size_t arrays = (12 + 4 + 1) * 8 * T + (4 + 1) * 4 * T;
+  // solver arrays (12), FP64 CG (7: every schedule's work arrays), refinement residual (1): double;
+  // FP32 CG (7) + correction (1): float
+  const size_t arrays = (12 + 7 + 1) * 8 * T + (7 + 1) * 4 * T;
   const size_t dense = 3 * 8 * n;  // initial guess, u and phi outputs
   // block partials, scalars, atom arrays and the cell list (with slack)
   const size_t small = (size_t)(max_stencil_blocks(g, 4096) + 4 * kPointwiseBlocks) * 16 * 8 + 128 * (size_t)s->M +
@@ -1351,7 +1511,7 @@ int alofdft_set_tuning(alofdft_ctx* c, int stencil_variant, int target_blocks, i
 }
 
 int alofdft_set_cg_schedule(alofdft_ctx* c, int schedule) {
-  if (!c || schedule < 0 || schedule > 1) return ALOFDFT_INVALID_ARGUMENT;
+  if (!c || schedule < -1 || schedule > 2) return ALOFDFT_INVALID_ARGUMENT;
   c->cg_schedule = schedule;
   return ALOFDFT_OK;
 }
@@ -1363,12 +1523,15 @@ int alofdft_profile_cg_kernel(alofdft_ctx* c, int sample_every) {
     c->prof_count[i] = 0;
     c->prof_ms[i] = 0.0;
     c->prof_points[i] = 0;
+    c->prof_sched[i] = -1;
   }
   return ALOFDFT_OK;
 }
 
-int alofdft_cg_kernel_stats(alofdft_ctx* c, int dtype, long long* launches, double* mean_ms, long long* points) {
+int alofdft_cg_kernel_stats(alofdft_ctx* c, int dtype, long long* launches, double* mean_ms, long long* points,
+                            int* schedule) {
   if (!c || (dtype != 0 && dtype != 1) || !launches || !mean_ms || !points) return ALOFDFT_INVALID_ARGUMENT;
+  if (schedule) *schedule = c->prof_sched[dtype];
   *launches = c->prof_count[dtype];
   *mean_ms = c->prof_count[dtype] ? c->prof_ms[dtype] / c->prof_count[dtype] : 0.0;
   *points = c->prof_points[dtype];

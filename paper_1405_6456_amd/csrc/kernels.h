@@ -903,6 +903,216 @@ __global__ void __launch_bounds__(NT) k_cg_update(Geom g, CGP2Op<T> op) {
   block_reduce_store<1, NT>(red, o.parts_out + blockIdx.x);
 }
 
+// ----------------------------------------------------------------- ops: CG with one reduction per iteration
+// With w = A r and s = A p kept as vectors (Chronopoulos and Gear), the two inner
+// products an iteration needs, gamma = r.r and delta = w.r, come out of the same pass,
+// and p.Ap = delta - beta gamma / alpha_prev (A-conjugacy of the previous p and the
+// orthogonality of successive residuals), so one launch and one reduction make an
+// iteration.
+
+// Sums of components 0 and 1 of n two-component block partials, in a fixed order
+// (every thread of the block returns the same pair); both components of a partial
+// come in one load.
+template <int NT>
+__device__ inline double2 block_sum_parts2(const double* parts, int n) {
+  __shared__ double sh[2][NT / 64];
+  const double2* pp = reinterpret_cast<const double2*>(parts);
+  double s0 = 0.0, s1 = 0.0;
+  for (int b0 = threadIdx.x; b0 < n; b0 += 8 * NT) {
+    double2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int b = b0 + u * NT;
+      v[u] = b < n ? pp[b] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      s0 += v[u].x;
+      s1 += v[u].y;
+    }
+  }
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = s0;
+    sh[1][threadIdx.x >> 6] = s1;
+  }
+  __syncthreads();
+  double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    t0 += sh[0][w];
+    t1 += sh[1][w];
+  }
+  __syncthreads();
+  return make_double2(t0, t1);
+}
+
+// Prologue of a one-reduction iteration k: gamma = r.r and delta = w.r from the
+// previous pass; stop at gamma <= tol^2 ||rhs||^2 (or, with last set, only record
+// gamma: the iteration cap was reached); else beta = gamma / gamma_prev and alpha =
+// gamma / (delta - beta gamma / alpha_prev).  Block 0 keeps gamma and alpha in CGState
+// indexed by k parity (no block reads a value written by the same launch).
+template <int NT>
+__device__ inline bool cg1r_prologue(CGState* st, const double* parts_in, int nparts_in, int k, int last, double& a,
+                                     double& b) {
+  if (st->done) return false;
+  const double2 gd = block_sum_parts2<NT>(parts_in, nparts_in);
+  const double gam = gd.x, del = gd.y;
+  if (!isfinite(gam) || !isfinite(del) || gam <= st->thresh || last) {
+    if (is_block0_thread0()) {
+      if (!isfinite(gam) || !isfinite(del)) st->done = 2;
+      else if (gam <= st->thresh) st->done = 1;
+      st->rr_last = gam;
+      st->rrh[k & 1] = gam;
+      st->iter = k;
+    }
+    return false;
+  }
+  b = k == 0 ? 0.0 : gam / st->rrh[(k - 1) & 1];
+  const double den = k == 0 ? del : del - b * gam / st->ah[(k - 1) & 1];
+  a = gam / den;
+  if (!(den > 0.0) || !isfinite(a)) {
+    // p.Ap <= 0 from finite scalars: the recurrences have drifted to rounding level
+    // (verdict 4, the caller restarts from the true residual); else non-finite (2)
+    if (is_block0_thread0()) {
+      st->done = (isfinite(den) && den <= 0.0) ? 4 : 2;
+      st->rr_last = gam;
+      st->rrh[k & 1] = gam;
+      st->iter = k;
+    }
+    return false;
+  }
+  if (is_block0_thread0()) {
+    st->rrh[k & 1] = gam;
+    st->ah[k & 1] = a;
+    st->iter = k;
+  }
+  return true;
+}
+
+// Start of the recurrences: w = A r for the residual r of the initial guess, p = s = 0,
+// reducing r.r and w.r.  The prologue takes ||rhs||^2 from the partials of the pass
+// that formed r (component 1 of 2) and fixes the stopping threshold.
+template <typename T>
+struct CGWInitOp {
+  static constexpr int NRED = 2;
+  static constexpr bool NEEDC = true;
+  static constexpr bool LATE_BEGIN = true;  // the stencil input r needs no scalar
+  const T* r;
+  T* w;
+  T* s;
+  T* p;
+  T* z;  // pipelined form only (else null): z = A s starts at 0 too
+  CGState* st;
+  const double* parts_in;
+  int nparts_in;
+  double tol2;
+  double* parts_out;
+  template <int NT>
+  __device__ bool begin() {
+    const double rhs2 = block_sum_parts<NT>(parts_in, nparts_in, 2, 1);
+    if (is_block0_thread0()) {
+      st->rhs2 = rhs2;
+      st->thresh = tol2 * rhs2;
+    }
+    if (rhs2 == 0.0) {
+      if (is_block0_thread0()) { st->done = 3; st->rr_last = 0.0; st->iter = 0; }
+      return false;
+    }
+    return true;
+  }
+  __device__ T load(long long i) const { return r[i]; }
+  __device__ void store(long long i, int, int, int, T c, T ar, double* red) const {
+    w[i] = ar;
+    s[i] = T(0);
+    p[i] = T(0);
+    if (z) z[i] = T(0);
+    red[0] += (double)c * (double)c;
+    red[1] += (double)ar * (double)c;
+  }
+  __device__ T loadb(uint32_t nb, uint32_t vo, uint32_t so) const { return bld(r, nb, vo, so); }
+  __device__ void storeb(uint32_t nb, uint32_t vo, uint32_t so, int, int, int, T c, T ar, double* red) const {
+    bst(w, nb, vo, so, ar);
+    bst(s, nb, vo, so, T(0));
+    bst(p, nb, vo, so, T(0));
+    if (z) bst(z, nb, vo, so, T(0));
+    red[0] += (double)c * (double)c;
+    red[1] += (double)ar * (double)c;
+  }
+};
+
+// Iterate k in the pipelined form (Ghysels and Vanroose): z = A s is kept as a vector
+// too, so the stencil is applied to w, an array already stored, and needs no scalar
+// of this iteration -- its loads go out before the prologue's reduction:
+//   m = A w,  z = m + beta z,  s = w + beta s,  p = r + beta p,  x += alpha p,
+//   r -= alpha s,  w' = w - alpha z,  reducing r.r and w'.r.
+// w is read at the stencil's neighbours, so it alternates between two arrays; the
+// others are touched only at the node itself, in place.  w and r are recurrences here
+// (rounding drifts them from A r and rhs - A x; the refined solve recomputes the
+// residual in FP64).
+template <typename T>
+struct CGPipeOp {
+  static constexpr int NRED = 2;
+  static constexpr bool NEEDC = true;
+  static constexpr bool LATE_BEGIN = true;  // the stencil input w needs no scalar
+  const T* w;
+  T* wn;
+  T* r;
+  T* s;
+  T* z;
+  T* p;
+  T* x;
+  CGState* st;
+  const double* parts_in;
+  int nparts_in, k, last;
+  double* parts_out;
+  T alpha, beta;
+  template <int NT>
+  __device__ bool begin() {
+    double a, b;
+    if (!cg1r_prologue<NT>(st, parts_in, nparts_in, k, last, a, b)) return false;
+    alpha = (T)a;
+    beta = (T)b;
+    return true;
+  }
+  __device__ T load(long long i) const { return w[i]; }
+  __device__ void store(long long i, int, int, int, T c, T m, double* red) const {
+    const T zi = m + beta * z[i];
+    const T si = c + beta * s[i];
+    const T pi = r[i] + beta * p[i];
+    const T ri = r[i] - alpha * si;
+    const T wi = c - alpha * zi;
+    z[i] = zi;
+    s[i] = si;
+    p[i] = pi;
+    x[i] += alpha * pi;
+    r[i] = ri;
+    wn[i] = wi;
+    red[0] += (double)ri * (double)ri;
+    red[1] += (double)wi * (double)ri;
+  }
+  __device__ T loadb(uint32_t nb, uint32_t vo, uint32_t so) const { return bld(w, nb, vo, so); }
+  __device__ void storeb(uint32_t nb, uint32_t vo, uint32_t so, int, int, int, T c, T m, double* red) const {
+    const T zo = bld((const T*)z, nb, vo, so), so_ = bld((const T*)s, nb, vo, so);
+    const T ro = bld((const T*)r, nb, vo, so), po = bld((const T*)p, nb, vo, so);
+    const T xo = bld((const T*)x, nb, vo, so);
+    const T zi = m + beta * zo;
+    const T si = c + beta * so_;
+    const T pi = ro + beta * po;
+    const T ri = ro - alpha * si;
+    const T wi = c - alpha * zi;
+    bst(z, nb, vo, so, zi);
+    bst(s, nb, vo, so, si);
+    bst(p, nb, vo, so, pi);
+    bst(x, nb, vo, so, xo + alpha * pi);
+    bst(r, nb, vo, so, ri);
+    bst(wn, nb, vo, so, wi);
+    red[0] += (double)ri * (double)ri;
+    red[1] += (double)wi * (double)ri;
+  }
+};
+
 // ----------------------------------------------------------------- ops: density updates
 // Position of node (i,j,k) relative to the box centre.
 struct BoxFrame {

@@ -125,11 +125,13 @@ template <class Op>
 struct is_cg_linear : std::false_type {};
 template <typename T>
 struct is_cg_linear<CGP1LOp<T>> : std::true_type {};
+template <typename T>
+struct is_cg_linear<CGPipeOp<T>> : std::true_type {};
 
 template <int R, typename T, class Op>
 hipError_t launch_stencil_r(const LaunchCfg& lc, const Geom& g, const StencilW<T>& W, const Op& op, int* nblocks) {
-  // the CG first half by linearity: streaming kernel over 64x8 tiles (forward
-  // accumulation for variants 11..16)
+  // the CG first half by linearity and the pipelined CG iteration: streaming kernel
+  // over 64x8 tiles (forward accumulation for variants 11..16)
   if constexpr (is_cg_linear<Op>::value) {
     const int var = lc.variant >= 100 ? lc.variant - 100 : lc.variant;
     const int alt = lc.variant >= 100 ? 0 : 1;
@@ -207,6 +209,10 @@ ALOFDFT_INST(float, CGP1Op<float>)
 ALOFDFT_INST(double, GradOp)
 ALOFDFT_INST(double, CGP1LOp<double>)
 ALOFDFT_INST(float, CGP1LOp<float>)
+ALOFDFT_INST(double, CGWInitOp<double>)
+ALOFDFT_INST(float, CGWInitOp<float>)
+ALOFDFT_INST(double, CGPipeOp<double>)
+ALOFDFT_INST(float, CGPipeOp<float>)
 #undef ALOFDFT_INST
 
 }  // namespace alofdft

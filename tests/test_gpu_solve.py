@@ -52,12 +52,17 @@ def test_small_pair_matches_oracle_live(C, pair_ref, method):
 
 @pytest.mark.parametrize("name", ["single", "fcc2"])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_workload_matches_oracle_fixture(C, name, precision):
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_workload_matches_oracle_fixture(C, name, precision, schedule):
     import paper_1405_6456_amd as lib
 
     gold = golden(name)
     S = synth.config(name)
-    out = C.solve(S, lib.default_params(precision=precision), synth.initial_u(S.grid, S.N))
+    C.set_cg_schedule(schedule)
+    try:
+        out = C.solve(S, lib.default_params(precision=precision), synth.initial_u(S.grid, S.N))
+    finally:
+        C.set_cg_schedule(-1)
     assert out["status"] == 0
     etol = E_TOL_FP64 if precision == 0 else E_TOL_MIXED
     assert abs(out["E_total"] - gold["result"]["E_total"]) / S.M < etol
@@ -68,8 +73,8 @@ def test_workload_matches_oracle_fixture(C, name, precision):
     assert np.abs(us - np.array(gold["u_samples"])).max() < 1e-4 * np.abs(u).max()
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_fcc5_solution_is_the_oracle_minimiser(C, orc, precision):
+@pytest.mark.parametrize("precision,schedule", [(0, 1), (1, 1), (0, 2)])
+def test_fcc5_solution_is_the_oracle_minimiser(C, orc, precision, schedule):
     # 500 atoms, 109^3 nodes: instead of a full oracle minimisation (hours on the host),
     # check the defining property of the result with the oracle's own arithmetic.  The
     # discrete minimiser under C_h(u) = 0 is unique; at the GPU's u* with its multiplier
@@ -80,7 +85,11 @@ def test_fcc5_solution_is_the_oracle_minimiser(C, orc, precision):
     import paper_1405_6456_amd as lib
 
     S = synth.config("fcc5")
-    out = C.solve(S, lib.default_params(precision=precision), synth.initial_u(S.grid, S.N))
+    C.set_cg_schedule(schedule)
+    try:
+        out = C.solve(S, lib.default_params(precision=precision), synth.initial_u(S.grid, S.N))
+    finally:
+        C.set_cg_schedule(-1)
     assert out["status"] == 0
     assert abs(out["C_h"]) / S.N < 1e-8
     prm = orc.params()

@@ -113,9 +113,10 @@ def _gauss_rho(g, charges):
 
 @pytest.mark.parametrize("bc", [0, 1])
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("schedule", [0, 1, 2])
 def test_poisson_matches_oracle(C, orc, bc, precision, schedule):
-    # both CG schedules (stencil of p; stencil of r with A p by linearity) reach the oracle's solution
+    # every CG schedule (stencil of p; stencil of r with A p by linearity; pipelined,
+    # one launch and one reduction) reaches the oracle's solution
     g = synth.Grid((41, 38, 35), 0.45, (-9.0, -8.3, -7.6))
     rho = _gauss_rho(g, [(1.0, (0.3, -0.4, 0.2), 1.0), (-0.7, (-1.1, 0.8, -0.3), 0.9)])
     rhs = orc.poisson_rhs(g, 6, bc, rho)
@@ -124,12 +125,12 @@ def test_poisson_matches_oracle(C, orc, bc, precision, schedule):
     try:
         phi, its, rel = C.poisson(dev(rho), g, bc=bc, precision=precision, tol=1e-11)
     finally:
-        C.set_cg_schedule(1)
+        C.set_cg_schedule(-1)
     assert rel < 1e-11
     assert np.abs(phi.cpu().numpy() - ref).max() <= 1e-8 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("schedule", [0, 1, 2])
 def test_poisson_iteration_cap(C, schedule):
     # stopped by the cap: exactly max_cg iterations and the true relative residual of the last iterate
     import torch
@@ -140,12 +141,34 @@ def test_poisson_iteration_cap(C, schedule):
     try:
         phi, its, rel = C.poisson(rho, g, bc=0, tol=1e-14, max_cg=37)
     finally:
-        C.set_cg_schedule(1)
+        C.set_cg_schedule(-1)
     assert its == 37
     # residual of the returned phi, recomputed with the stencil
     A_phi = -C.apply_laplacian(phi, g.h, 6) / (4 * math.pi)
     true_rel = float(torch.linalg.norm(rho - A_phi) / torch.linalg.norm(rho))
     assert abs(true_rel - rel) <= 1e-6 * true_rel + 1e-12
+
+
+def test_cg_schedule_automatic(C):
+    # default: FP64 solves on small grids run pipelined, FP32 inner solves and FP64
+    # solves on large grids run the two-launch schedule 1
+    import torch
+
+    g = synth.Grid((40, 36, 33), 0.5, (0.0, 0.0, 0.0))
+    rho = torch.from_numpy(synth.random_field(g, 21)).cuda()
+    big = synth.Grid((120, 118, 116), 0.5, (0.0, 0.0, 0.0))
+    rho_big = torch.from_numpy(synth.random_field(big, 22)).cuda()
+    C.profile_cg_kernel(1)
+    try:
+        _, _, rel = C.poisson(rho, g, bc=0, precision=0, tol=1e-9)
+        assert C.cg_kernel_stats(0)[3] == 2 and rel < 1e-9
+        C.poisson(rho, g, bc=0, precision=1, tol=1e-9)
+        assert C.cg_kernel_stats(1)[3] == 1
+        C.profile_cg_kernel(1)
+        C.poisson(rho_big, big, bc=0, precision=0, tol=1e-9, max_cg=20)
+        assert C.cg_kernel_stats(0)[3] == 1
+    finally:
+        C.profile_cg_kernel(0)
 
 
 def test_poisson_gaussian_closed_form(C):
@@ -163,23 +186,51 @@ def test_poisson_gaussian_closed_form(C):
     assert np.abs(phi.cpu().numpy() - exact).max() < 1e-7
 
 
-def test_poisson_warm_start_from_solution(C, orc):
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_poisson_warm_start_from_solution(C, orc, schedule):
     # restarting from a converged solution needs at most a couple of iterations (the
     # recomputed residual differs from the recursively updated one by rounding)
     g = synth.Grid((33, 33, 33), 0.5, (-8.0, -8.0, -8.0))
     rho = _gauss_rho(g, [(1.0, (0.2, 0.1, -0.3), 1.0)])
-    phi, its, rel = C.poisson(dev(rho), g, bc=1, tol=1e-10)
-    phi2, its2, rel2 = C.poisson(dev(rho), g, phi0=phi, bc=1, tol=1e-10)
+    C.set_cg_schedule(schedule)
+    try:
+        phi, its, rel = C.poisson(dev(rho), g, bc=1, tol=1e-10)
+        phi2, its2, rel2 = C.poisson(dev(rho), g, phi0=phi, bc=1, tol=1e-10)
+    finally:
+        C.set_cg_schedule(-1)
     assert its > 50 and its2 <= 3 and rel2 < 1e-10
 
 
-def test_poisson_zero_rhs(C):
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_poisson_zero_rhs(C, schedule):
     g = synth.Grid((21, 21, 21), 0.5, (0.0, 0.0, 0.0))
     import torch
 
-    phi, its, rel = C.poisson(torch.zeros(g.shape, dtype=torch.float64, device="cuda:0"), g,
-                              phi0=torch.ones(g.shape, dtype=torch.float64, device="cuda:0"), bc=0)
+    C.set_cg_schedule(schedule)
+    try:
+        phi, its, rel = C.poisson(torch.zeros(g.shape, dtype=torch.float64, device="cuda:0"), g,
+                                  phi0=torch.ones(g.shape, dtype=torch.float64, device="cuda:0"), bc=0)
+    finally:
+        C.set_cg_schedule(-1)
     assert its == 0 and float(phi.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("schedule", [2])
+def test_poisson_one_reduction_iterates_follow_cg(C, orc, schedule):
+    # the pipelined recurrences are CG in exact arithmetic: in FP64, with the iteration
+    # cap at k, the iterate is the k-th CG iterate of the two-launch schedule up to
+    # rounding (k small, so rounding has not yet been amplified)
+    g = synth.Grid((37, 34, 31), 0.5, (0.0, 0.0, 0.0))
+    rho = dev(synth.random_field(g, 23))
+    out = {}
+    for sch in (1, schedule):
+        C.set_cg_schedule(sch)
+        try:
+            out[sch] = [C.poisson(rho, g, bc=0, tol=1e-14, max_cg=k)[0].cpu().numpy() for k in (1, 5, 20)]
+        finally:
+            C.set_cg_schedule(-1)
+    for a, b in zip(out[1], out[schedule]):
+        assert np.abs(a - b).max() <= 1e-9 * np.abs(a).max()
 
 
 # ---------------------------------------------------------------- nuclei
