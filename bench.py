@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--cg-schedule", type=int, default=-1, choices=[-1, 0, 1, 2],
                     help="CG launches per iteration: 0/1 two launches, 2 pipelined (one launch, FP64 only), "
                          "-1 the library's automatic choice")
-    ap.add_argument("--mode", default="solve", choices=["solve", "stencil", "counters", "serve"],
+    ap.add_argument("--mode", default="solve", choices=["solve", "stencil", "counters", "serve", "relax"],
                     help="stencil: only the streaming stencil measurement; counters: a short refined "
                          "Poisson solve and a reference copy (for counter passes); serve: the request "
                          "stream of fcc 1-3 clusters through the serving loop")
@@ -262,6 +262,37 @@ def serve(args):
     print(json.dumps(line), flush=True)
 
 
+def relax_mode():
+    """Relaxation of the two-atom analogue of the paper's Al2 case (Z = 3, Gaussian
+    pseudocharges, 27^3 nodes at h = 0.9 Bohr) from 4.0 Bohr apart to ftol = 2e-4 Ha/Bohr:
+    wall time, nonlinear CG steps, ground-state solves and the bond length reached."""
+    import numpy as np
+    import torch
+
+    import paper_1405_6456_amd as lib
+    from paper_1405_6456_amd import synth
+
+    n, h = 27, 0.9
+    g = synth.Grid((n, n, n), h, (0.0, 0.0, 0.0))
+    c = 0.5 * (n - 1) * h
+    R = np.array([[c, c, c - 2.0], [c + 0.05, c - 0.1, c + 2.0]])
+    S = synth.System("pair", g, R, np.array([3.0, 3.0]), 6.0)
+    ctx = lib.Context(0)
+    u0 = synth.initial_u(g, S.N)
+    ctx.solve(S, lib.default_params(), u0, want_fields=False)  # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    out = ctx.relax(S, lib.default_params(), lib.default_relax_params(ftol=2e-4), u0)
+    wall = time.perf_counter() - t
+    d = float(np.linalg.norm(out["R"][1] - out["R"][0]))
+    print(json.dumps({"mode": "relax", "workload": "pair, Z=3, 27^3 nodes, h=0.9, from 4.0 Bohr, ftol 2e-4",
+                      "wall_s": round(wall, 3), "steps": out["steps"], "solves": out["solves"],
+                      "ms_per_solve": round(1e3 * wall / max(1, out["solves"]), 1), "fmax": out["fmax"],
+                      "bond_bohr": round(d, 4), "E_total": out["E_total"], "status": out["relax_status"]}),
+          flush=True)
+    ctx.close()
+
+
 def counters_mode(S, schedule, precision):
     """A short Poisson solve on the workload grid in the bench's precision for it (its CG
     kernel is the one of interest), then a 256 MiB reference copy whose counter readings
@@ -308,6 +339,8 @@ def main():
     torch.cuda.set_device(0)
     if args.mode == "serve":
         return serve(args)
+    if args.mode == "relax":
+        return relax_mode()
     S = synth.config(args.workload)
     if args.mode == "counters":
         return counters_mode(S, args.cg_schedule, args.precision)

@@ -166,6 +166,47 @@ int alofdft_solve_device(alofdft_ctx* ctx, const alofdft_system* sys, const alof
                          const double* u0_dev, double* u_out_dev, double* phi_out_dev, double* forces_out,
                          alofdft_result* res);
 
+/* Relaxation of the nuclei to the ground-state configuration (Sec. 4: Polak-Ribiere
+ * nonlinear CG with a secant line search over the 3M positions).  The objective is
+ * the ground-state energy E(R) of alofdft_solve, its gradient minus the forces;
+ * every evaluation is a full solve at that geometry, warm-started from the previous
+ * evaluation's u and phi.  One line-search step: a probe of length `probe` (largest
+ * atom displacement, Bohr), then secant steps on the directional derivative
+ * -F . d until |F . d| <= secant_rel |F0 . d| or max_secant evaluations; the last
+ * evaluated point is accepted.  No step moves an atom more than max_move, nor its
+ * r_cut ball out of the box.  Stops when every atom's |F| < ftol (Ha/Bohr). */
+typedef struct {
+  double ftol;       /* force threshold, Ha/Bohr (default 1e-3) */
+  double max_move;   /* largest displacement of one atom per step, Bohr (0.3) */
+  double probe;      /* largest displacement of the first trial of a line, Bohr (0.05) */
+  int max_steps;     /* nonlinear CG steps (50) */
+  int max_secant;    /* solves per line search (3) */
+  double secant_rel; /* directional-derivative reduction that ends a line search (0.1) */
+} alofdft_relax_params;
+
+typedef struct {
+  int status;        /* OK (converged), NOT_CONVERGED (step cap or an atom at the box edge), or an error */
+  int steps;         /* nonlinear CG steps taken */
+  int solves;        /* ground-state solves */
+  double fmax;       /* largest |F| of an atom at R_out */
+  double E_total;    /* energy at R_out */
+} alofdft_relax_info;
+
+/* Fills *p with the defaults above.  INVALID_ARGUMENT for NULL. */
+int alofdft_default_relax_params(alofdft_relax_params* p);
+
+/*   sys        the starting geometry (its R is not modified); prm as for alofdft_solve.
+ *   u0         host grid array, nullable (as for alofdft_solve), guess of the first solve.
+ *   R_out      host 3*M, required: relaxed positions.
+ *   forces_out host 3*M, nullable: forces at R_out.
+ *   res        required: the result of the solve at R_out.  info required.
+ * Returns info->status.  Errors: those of alofdft_solve (from any evaluation);
+ * INVALID_ARGUMENT for a null pointer or parameters out of range (ftol, max_move,
+ * probe > 0; max_steps, max_secant >= 1; 0 < secant_rel < 1). */
+int alofdft_relax(alofdft_ctx* ctx, const alofdft_system* sys, const alofdft_params* prm,
+                  const alofdft_relax_params* rp, const double* u0, double* R_out, double* forces_out,
+                  alofdft_result* res, alofdft_relax_info* info);
+
 /* y = Delta_h x, the order-2*fd_half_width stencil of Eq. FD:Laplacian with zero
  * ghosts.  x_dev, y_dev: device grid arrays of n[0]*n[1]*n[2] elements of type
  * dtype (0 = double, 1 = float).  Returns INVALID_ARGUMENT for bad sizes. */

@@ -62,6 +62,16 @@ class ServerStats(C.Structure):
                [(k, C.c_double) for k in ("p50_ms", "p99_ms", "mean_ms", "solves_per_s", "hbm_reserved_bytes")]
 
 
+class RelaxParams(C.Structure):
+    _fields_ = [("ftol", C.c_double), ("max_move", C.c_double), ("probe", C.c_double), ("max_steps", C.c_int),
+                ("max_secant", C.c_int), ("secant_rel", C.c_double)]
+
+
+class RelaxInfo(C.Structure):
+    _fields_ = [("status", C.c_int), ("steps", C.c_int), ("solves", C.c_int), ("fmax", C.c_double),
+                ("E_total", C.c_double)]
+
+
 class AlofdftError(RuntimeError):
     def __init__(self, status, detail=""):
         super().__init__(f"alofdft status {status}: {detail}")
@@ -94,6 +104,9 @@ def lib():
                                     C.POINTER(Result)]
         L.alofdft_solve_device.argtypes = [_VP, C.POINTER(SystemS), C.POINTER(Params), _VP, _VP, _VP, _DP,
                                            C.POINTER(Result)]
+        L.alofdft_default_relax_params.argtypes = [C.POINTER(RelaxParams)]
+        L.alofdft_relax.argtypes = [_VP, C.POINTER(SystemS), C.POINTER(Params), C.POINTER(RelaxParams), _DP, _DP,
+                                    _DP, C.POINTER(Result), C.POINTER(RelaxInfo)]
         L.alofdft_apply_laplacian.argtypes = [_VP, C.POINTER(C.c_int), C.c_double, C.c_int, C.c_int, _VP, _VP]
         L.alofdft_poisson.argtypes = [_VP, C.POINTER(C.c_int), C.c_double, _DP, C.c_int, C.c_int, C.c_int, _VP,
                                       _VP, C.c_double, C.c_int, C.POINTER(C.c_longlong), _DP]
@@ -124,6 +137,16 @@ def default_params(**kw) -> Params:
     lib().alofdft_default_params(C.byref(p))
     for k, v in kw.items():
         setattr(p, "lambda_" if k == "lambda" else k, v)
+    return p
+
+
+def default_relax_params(**kw) -> RelaxParams:
+    """Relaxation defaults (ftol 1e-3 Ha/Bohr, max_move 0.3 Bohr, probe 0.05 Bohr, 50 steps,
+    3 solves per line search, secant_rel 0.1) with overrides."""
+    p = RelaxParams()
+    lib().alofdft_default_relax_params(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
     return p
 
 
@@ -216,6 +239,25 @@ class Context:
         _check(self, st, (OK, NOT_CONVERGED))
         out = result_dict(res)
         out.update(u=u, phi=phi, forces=f)
+        return out
+
+    def relax(self, system, params: Params | None = None, relax: RelaxParams | None = None, u0=None):
+        """Relaxes the nuclei from system.R (Polak-Ribiere nonlinear CG with a secant line
+        search, every evaluation a full solve).  Returns a dict with R, forces, the final
+        solve's result fields and steps, solves, fmax, relax_status."""
+        params = params or default_params()
+        relax = relax or default_relax_params()
+        S = SystemArgs(system)
+        R = np.zeros((S.s.M, 3))
+        f = np.zeros((S.s.M, 3))
+        u0c = None if u0 is None else np.ascontiguousarray(u0, dtype=np.float64)
+        res, info = Result(), RelaxInfo()
+        st = lib().alofdft_relax(self.handle, C.byref(S.s), C.byref(params), C.byref(relax),
+                                 None if u0c is None else u0c.ctypes.data_as(_DP), R.ctypes.data_as(_DP),
+                                 f.ctypes.data_as(_DP), C.byref(res), C.byref(info))
+        _check(self, st, (OK, NOT_CONVERGED))
+        out = result_dict(res)
+        out.update(R=R, forces=f, steps=info.steps, solves=info.solves, fmax=info.fmax, relax_status=info.status)
         return out
 
     def solve_device(self, system, params=None, u0=None, u_out=None, phi_out=None, want_forces=True):

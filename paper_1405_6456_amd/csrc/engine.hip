@@ -328,11 +328,14 @@ bool sampled(const alofdft_ctx* c, long long k) {
 }
 
 // Kernel-stamped event pair number `used` of the context's pool (created on demand).
+// The events only time the kernel they stamp: without the system-scope fence their
+// recording neither writes back nor invalidates the caches, which would lengthen the
+// stamped kernel and slow the next.
 std::pair<hipEvent_t, hipEvent_t> prof_pair(alofdft_ctx* c, size_t used) {
   if (used == c->prof_pool.size()) {
     hipEvent_t a, b;
-    HIPC(c, hipEventCreate(&a));
-    HIPC(c, hipEventCreate(&b));
+    HIPC(c, hipEventCreateWithFlags(&a, hipEventDisableSystemFence));
+    HIPC(c, hipEventCreateWithFlags(&b, hipEventDisableSystemFence));
     c->prof_pool.push_back({a, b});
   }
   return c->prof_pool[used];
@@ -507,16 +510,7 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
     if (sched == 1) op1.pold = op1.pnew = p0;  // p and A p updated in place
     const bool timed = sampled(c, k);
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (timed) {
-      if (pool_used == c->prof_pool.size()) {
-        hipEvent_t a, b;
-        HIPC(c, hipEventCreate(&a));
-        HIPC(c, hipEventCreate(&b));
-        c->prof_pool.push_back({a, b});
-      }
-      e0 = c->prof_pool[pool_used].first;
-      e1 = c->prof_pool[pool_used].second;
-    }
+    if (timed) std::tie(e0, e1) = prof_pair(c, pool_used);
     const int nb1 = sched == 1 ? launch_stencil(c, g, A, CGP1LOp<T>{op1}, e0, e1)
                                         : launch_stencil(c, g, A, op1, e0, e1);  // events stamp the kernel itself
     if (timed) pending.push_back({k, pool_used++});
@@ -850,9 +844,11 @@ class Solver {
     CF_ = 0.3 * std::pow(3.0 * M_PI * M_PI, 2.0 / 3.0);
   }
 
-  // Zero all work arrays (halo included) and set up the nuclei.
-  void setup(const double* u0_dense_dev, bool u0_abs) {
-    for (double* a : {us_, v_, d_, sa_, sb_, b_, phi_, rhs_, ph_[0], ph_[1], ph_[2]}) fill<double>(c_, a, g_.total, 0.0);
+  // Zero all work arrays (halo included) and set up the nuclei.  warm_phi keeps phi
+  // from the context's previous solve on the same grid as the first Poisson guess.
+  void setup(const double* u0_dense_dev, bool u0_abs, bool warm_phi = false) {
+    for (double* a : {us_, v_, d_, sa_, sb_, b_, rhs_, ph_[0], ph_[1], ph_[2]}) fill<double>(c_, a, g_.total, 0.0);
+    if (!warm_phi) fill<double>(c_, phi_, g_.total, 0.0);
     at_ = upload_atoms(c_, S_, P_->r_cut);
     pseudocharge_dev(c_, g_, S_, at_, P_->gauss_width, P_->r_cut, b_);
     std::vector<double> self;
@@ -1261,7 +1257,8 @@ std::vector<double> default_u0(const alofdft_system* s, uint64_t seed) {
 long long npoints(const int n[3]) { return (long long)n[0] * n[1] * n[2]; }
 
 int solve_impl(alofdft_ctx* c, const alofdft_system* sys, const alofdft_params* prm, const double* u0_dev,
-               const double* u0_host, double* u_out_dev, double* phi_out_dev, double* forces, alofdft_result* res) {
+               const double* u0_host, double* u_out_dev, double* phi_out_dev, double* forces, alofdft_result* res,
+               bool warm_phi = false) {
   require(c, res != nullptr, "result pointer is null");
   std::memset(res, 0, sizeof(*res));
   validate(c, sys, prm);
@@ -1277,13 +1274,120 @@ int solve_impl(alofdft_ctx* c, const alofdft_system* sys, const alofdft_params* 
     sync(c);
   }
   Solver S(c, sys, prm);
-  S.setup(u0, true);
+  S.setup(u0, true, warm_phi);
   int st = S.run(res);
   S.output(u_out_dev, phi_out_dev);
   if (forces) S.forces(forces);
   sync(c);
   res->time_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return st;
+}
+
+// ----------------------------------------------------------------- relaxation of the nuclei
+// Ground-state configuration of the nuclei (Sec. 4): Polak-Ribiere nonlinear CG over the
+// 3M positions with a secant line search, on E(R) (the ground-state energy) whose
+// gradient is -F(R).  Every evaluation is a full solve at that geometry, warm-started from
+// the last u and, on the same grid, the last phi.  Steps are capped so that no atom moves
+// more than max_move and every r_cut ball stays in the box.
+int relax_impl(alofdft_ctx* c, const alofdft_system* sys, const alofdft_params* prm, const alofdft_relax_params* rp,
+               const double* u0_host, double* R_out, double* forces_out, alofdft_result* res,
+               alofdft_relax_info* info) {
+  require(c, rp && R_out && res && info, "null argument");
+  require(c, rp->ftol > 0 && rp->max_move > 0 && rp->probe > 0 && rp->max_steps >= 1 && rp->max_secant >= 1 &&
+                 rp->secant_rel > 0 && rp->secant_rel < 1,
+          "relaxation parameters out of range");
+  validate(c, sys, prm);
+  std::memset(info, 0, sizeof(*info));
+  const int M = sys->M, D = 3 * M;
+  const long long n = npoints(sys->n);
+  double* udev = bufT<double>(c, "relax.u", (size_t)n);
+  std::vector<double> R(sys->R, sys->R + D), F(D), Ft(D), Rt(D), d(D), Fold(D);
+  alofdft_result r{};
+  bool first = true;
+  auto evaluate = [&](const std::vector<double>& X, std::vector<double>& G, alofdft_result& out) {
+    alofdft_system s = *sys;
+    s.R = X.data();
+    const int st = solve_impl(c, &s, prm, first ? nullptr : udev, first ? u0_host : nullptr, udev, nullptr, G.data(),
+                              &out, !first);
+    first = false;
+    info->solves++;
+    if (st < 0) throw Fail{st};  // the solve's own status and message
+    return st;
+  };
+  auto dot = [&](const std::vector<double>& a, const std::vector<double>& b) {
+    double t = 0.0;
+    for (int i = 0; i < D; ++i) t += a[i] * b[i];
+    return t;
+  };
+  auto fmax_of = [&](const std::vector<double>& G) {
+    double m = 0.0;
+    for (int J = 0; J < M; ++J)
+      m = std::max(m, std::sqrt(G[3 * J] * G[3 * J] + G[3 * J + 1] * G[3 * J + 1] + G[3 * J + 2] * G[3 * J + 2]));
+    return m;
+  };
+  // largest step along d keeping every atom's move <= max_move and its r_cut ball in the box
+  auto max_alpha = [&](const std::vector<double>& X, const std::vector<double>& dir) {
+    double dmax = 0.0, amax = HUGE_VAL;
+    for (int J = 0; J < M; ++J) {
+      const double* v = &dir[3 * J];
+      dmax = std::max(dmax, std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
+      for (int a = 0; a < 3; ++a) {
+        const double lo = sys->origin[a] + prm->r_cut, hi = sys->origin[a] + (sys->n[a] - 1) * sys->h - prm->r_cut;
+        const double x = X[3 * J + a], va = v[a];
+        if (va > 0) amax = std::min(amax, (hi - x) / va);
+        if (va < 0) amax = std::min(amax, (lo - x) / va);
+      }
+    }
+    return std::make_pair(dmax, std::min(amax, dmax > 0 ? rp->max_move / dmax : 0.0));
+  };
+
+  int st = evaluate(R, F, r);
+  for (int i = 0; i < D; ++i) d[i] = F[i];
+  int status = ALOFDFT_NOT_CONVERGED;
+  for (int step = 0; step < rp->max_steps; ++step) {
+    info->fmax = fmax_of(F);
+    if (info->fmax < rp->ftol) { status = ALOFDFT_OK; break; }
+    info->steps = step + 1;
+    // secant on the directional derivative g(a) = -F(R + a d) . d, from g(0) < 0
+    const auto [dmax, amax] = max_alpha(R, d);
+    if (!(amax > 0)) break;  // an atom sits at the edge of the admissible region along d
+    const double g0 = -dot(F, d);
+    double a_prev = 0.0, g_prev = g0;
+    double a = std::min(rp->probe / dmax, amax);
+    for (int j = 0; j < rp->max_secant; ++j) {
+      for (int i = 0; i < D; ++i) Rt[i] = R[i] + a * d[i];
+      st = evaluate(Rt, Ft, r);
+      const double g = -dot(Ft, d);
+      if (std::fabs(g) <= rp->secant_rel * std::fabs(g0) || j == rp->max_secant - 1) break;
+      double an = a - g * (a - a_prev) / (g - g_prev);
+      // a curvature of the wrong sign or a root beyond the cap: expand towards the cap
+      if (!std::isfinite(an) || g - g_prev <= 0.0 || an > amax) an = std::min(2.0 * a, amax);
+      if (an <= 0.0) an = 0.5 * a;
+      if (an == a) break;
+      a_prev = a;
+      g_prev = g;
+      a = an;
+    }
+    // accept the last evaluated point (its forces are known)
+    Fold = F;
+    R = Rt;
+    F = Ft;
+    // Polak-Ribiere with restart when the new direction is not a descent direction
+    const double den = dot(Fold, Fold);
+    double beta = den > 0 ? (dot(F, F) - dot(F, Fold)) / den : 0.0;
+    beta = std::max(0.0, beta);
+    for (int i = 0; i < D; ++i) d[i] = F[i] + beta * d[i];
+    if (dot(F, d) <= 0.0)
+      for (int i = 0; i < D; ++i) d[i] = F[i];
+  }
+  info->fmax = fmax_of(F);
+  if (info->fmax < rp->ftol) status = ALOFDFT_OK;
+  std::copy(R.begin(), R.end(), R_out);
+  if (forces_out) std::copy(F.begin(), F.end(), forces_out);
+  *res = r;
+  info->E_total = r.E_total;
+  info->status = st != 0 ? st : status;
+  return info->status;
 }
 
 // ----------------------------------------------------------------- serving
@@ -1558,6 +1662,24 @@ int alofdft_solve_device(alofdft_ctx* c, const alofdft_system* sys, const alofdf
                          double* u_out_dev, double* phi_out_dev, double* forces_out, alofdft_result* res) {
   if (!c) return ALOFDFT_INVALID_ARGUMENT;
   return guarded(c, [&]() { return solve_impl(c, sys, prm, u0_dev, nullptr, u_out_dev, phi_out_dev, forces_out, res); });
+}
+
+int alofdft_default_relax_params(alofdft_relax_params* p) {
+  if (!p) return ALOFDFT_INVALID_ARGUMENT;
+  p->ftol = 1e-3;
+  p->max_move = 0.3;
+  p->probe = 0.05;
+  p->max_steps = 50;
+  p->max_secant = 3;
+  p->secant_rel = 0.1;
+  return ALOFDFT_OK;
+}
+
+int alofdft_relax(alofdft_ctx* c, const alofdft_system* sys, const alofdft_params* prm,
+                  const alofdft_relax_params* rp, const double* u0, double* R_out, double* forces_out,
+                  alofdft_result* res, alofdft_relax_info* info) {
+  if (!c) return ALOFDFT_INVALID_ARGUMENT;
+  return guarded(c, [&]() { return relax_impl(c, sys, prm, rp, u0, R_out, forces_out, res, info); });
 }
 
 int alofdft_apply_laplacian(alofdft_ctx* c, const int n[3], double h, int fdn, int dtype, const void* x, void* y) {

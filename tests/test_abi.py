@@ -19,7 +19,8 @@ def declared():
 def test_header_declares_the_boundary():
     names = declared()
     for n in ("alofdft_create", "alofdft_solve", "alofdft_solve_device", "alofdft_apply_laplacian",
-              "alofdft_poisson", "alofdft_energy_gradient", "alofdft_forces", "alofdft_pseudocharge"):
+              "alofdft_poisson", "alofdft_energy_gradient", "alofdft_forces", "alofdft_pseudocharge",
+              "alofdft_relax"):
         assert n in names
 
 
@@ -47,6 +48,11 @@ def test_host_only_calls():
     assert L.alofdft_default_params(None) == lib.INVALID_ARGUMENT
     assert L.alofdft_set_tuning(None, 0, 1024, 4) == lib.INVALID_ARGUMENT
     assert L.alofdft_set_cg_schedule(None, 1) == lib.INVALID_ARGUMENT
+    rp = lib.default_relax_params()
+    assert rp.ftol == 1e-3 and rp.max_move == 0.3 and rp.probe == 0.05 and rp.max_steps == 50
+    assert rp.max_secant == 3 and rp.secant_rel == 0.1
+    assert L.alofdft_default_relax_params(None) == lib.INVALID_ARGUMENT
+    assert L.alofdft_relax(None, None, None, None, None, None, None, None, None) == lib.INVALID_ARGUMENT
 
 
 def test_binding_refuses_without_gpu():
