@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--cg-schedule", type=int, default=-1, choices=[-1, 0, 1, 2],
                     help="CG launches per iteration: 0/1 two launches, 2 pipelined (one launch, FP64 only), "
                          "-1 the library's automatic choice")
-    ap.add_argument("--mode", default="solve", choices=["solve", "stencil", "counters", "serve", "relax"],
+    ap.add_argument("--mode", default="solve", choices=["solve", "stencil", "counters", "serve", "relax", "methods"],
                     help="stencil: only the streaming stencil measurement; counters: a short refined "
                          "Poisson solve and a reference copy (for counter passes); serve: the request "
                          "stream of fcc 1-3 clusters through the serving loop")
@@ -262,6 +262,44 @@ def serve(args):
     print(json.dumps(line), flush=True)
 
 
+def methods_mode():
+    """The paper's method comparison on the synthetic workloads (Sec. 5.3): the augmented
+    Lagrangian against the penalty method (eta fixed at 0) on the single atom and the 32-atom
+    cluster, and the augmented Lagrangian's sensitivity to eta0, mu0 and kappa on the single
+    atom -- stencil applications (the paper's cost measure), iterations, energy, time.  FP64."""
+    import numpy as np  # noqa: F401
+    import torch
+
+    import paper_1405_6456_amd as lib
+    from paper_1405_6456_amd import synth
+
+    ctx = lib.Context(0)
+
+    def run(name, **kw):
+        S = synth.config(name)
+        u0 = synth.initial_u(S.grid, S.N) if name == "single" else synth.atomic_guess(S)
+        u0d = torch.from_numpy(u0).to("cuda:0").contiguous()
+        prm = lib.default_params(precision=lib.FP64, **kw)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        o = ctx.solve_device(S, prm, u0d, want_forces=False)
+        wall = time.perf_counter() - t
+        line = {"mode": "methods", "workload": name, **kw, "status": o["status"], "matvecs": o["matvec_fp64"],
+                "outer": o["outer"], "inner": o["inner"], "E_per_atom": o["E_total"] / S.M, "eta_star": o["eta_star"],
+                "C_h_per_N": o["C_h"] / S.N, "wall_s": round(wall, 3)}
+        print(json.dumps(line), flush=True)
+        return o
+
+    run("single")  # warm-up
+    for name in ("single", "fcc2"):
+        for method in (lib.AL, lib.PENALTY):
+            run(name, method=method)
+    for eta0, mu0, kappa in ((0.0, 1.0, 0.1), (-0.4, 1.0, 0.1), (-0.2, 0.1, 0.1), (-0.2, 10.0, 0.1),
+                             (-0.2, 1.0, 0.01), (-0.2, 1.0, 0.5)):
+        run("single", eta0=eta0, mu0=mu0, kappa=kappa)
+    ctx.close()
+
+
 def relax_mode():
     """Relaxation of the two-atom analogue of the paper's Al2 case (Z = 3, Gaussian
     pseudocharges, 27^3 nodes at h = 0.9 Bohr) from 4.0 Bohr apart to ftol = 2e-4 Ha/Bohr:
@@ -341,6 +379,8 @@ def main():
         return serve(args)
     if args.mode == "relax":
         return relax_mode()
+    if args.mode == "methods":
+        return methods_mode()
     S = synth.config(args.workload)
     if args.mode == "counters":
         return counters_mode(S, args.cg_schedule, args.precision)
