@@ -318,6 +318,28 @@ int cg_schedule_for(const alofdft_ctx* c, const Geom& g, bool fp64) {
   return s;
 }
 
+// Host polls of a CG solve's state (each a copy and a stream synchronisation): first
+// after `every` launches, then timed by the residual reduction observed between polls so
+// that the poll lands just past the predicted last iteration (at most `every` launches
+// ahead) -- launches queued after convergence only run their prologue, but cost a launch.
+struct PollPlan {
+  long long every, next, k_last = 0;
+  double rr_last = -1.0;
+  PollPlan(long long e, long long first) : every(e), next(std::max(1LL, std::min(e, first))) {}
+  bool due(long long k) const { return k + 1 >= next; }
+  void update(long long k, double rr, double thresh) {
+    long long step = every;
+    if (rr_last > 0 && rr > thresh && rr < rr_last && thresh > 0) {
+      const double per_it = std::log(rr / rr_last) / (double)(k + 1 - k_last);  // < 0
+      const double need = std::log(thresh / rr) / per_it;                          // > 0
+      if (std::isfinite(need)) step = std::max(2LL, std::min(every, (long long)std::ceil(need) + 1));
+    }
+    rr_last = rr;
+    k_last = k + 1;
+    next = k + 1 + step;
+  }
+};
+
 // Whether CG launch k carries timing events: every prof_every-th launch, offset from
 // the host's polls of the solve state (every check_every launches), after which the
 // device has drained and the next launch starts cold.
@@ -347,7 +369,7 @@ std::pair<hipEvent_t, hipEvent_t> prof_pair(alofdft_ctx* c, size_t used) {
 template <typename T>
 CGResult cg_solve_pipe(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* rhs, T* x, double tol,
                        long long max_it, int check_every, const char* tag, bool init, const double* init_parts,
-                       int init_nparts, bool stop_on_stagnation) {
+                       int init_nparts, bool stop_on_stagnation, int first_poll) {
   const std::string t(tag);
   T* r = gridbuf<T>(c, t + ".r", g);
   T* wv[2] = {gridbuf<T>(c, t + ".w0", g), gridbuf<T>(c, t + ".w1", g)};
@@ -398,6 +420,7 @@ CGResult cg_solve_pipe(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, cons
   long long k = 0;
   double best_rr = HUGE_VAL;
   long long best_k = 0;
+  PollPlan poll(check_every, first_poll);
   for (;; ++k) {
     if (k >= max_it) break;
     const bool timed = sampled(c, k);
@@ -405,14 +428,15 @@ CGResult cg_solve_pipe(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, cons
     if (timed) std::tie(e0, e1) = prof_pair(c, pool_used);
     launch_k(k, 0, e0, e1);
     if (timed) pending.push_back({k, pool_used++});
-    if ((k + 1) % check_every == 0) {
+    if (poll.due(k)) {
       HIPC(c, hipMemcpyAsync(c->pin, st, sizeof(CGState), hipMemcpyDeviceToHost, c->stream));
       sync(c);
       const CGState* sp = (CGState*)c->pin;
       harvest(sp->done ? sp->iter : k + 1);
       if (sp->done) break;
+      const double rr = sp->rrh[sp->iter & 1];
+      poll.update(k, rr, sp->thresh);
       if (stop_on_stagnation) {
-        const double rr = sp->rrh[sp->iter & 1];
         if (rr < 0.5 * best_rr) {
           best_rr = rr;
           best_k = k;
@@ -453,11 +477,11 @@ CGResult cg_solve_pipe(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, cons
 template <typename T>
 CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* rhs, T* x, double tol, long long max_it,
                   int check_every, const char* tag, bool init = true, const double* init_parts = nullptr,
-                  int init_nparts = 0, bool stop_on_stagnation = false) {
+                  int init_nparts = 0, bool stop_on_stagnation = false, int first_poll = 1 << 30) {
   const int sched = cg_schedule_for(c, g, sizeof(T) == 8);
   if (sched == 2)
     return cg_solve_pipe<T>(c, g, A, rhs, x, tol, max_it, check_every, tag, init, init_parts, init_nparts,
-                            stop_on_stagnation);
+                            stop_on_stagnation, first_poll);
   const std::string t(tag);
   T* r = gridbuf<T>(c, t + ".r", g);
   T* p0 = gridbuf<T>(c, t + ".p0", g);
@@ -502,6 +526,7 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
   long long k = 0;
   double best_rr = HUGE_VAL;
   long long best_k = 0;
+  PollPlan poll(check_every, first_poll);
   for (;; ++k) {
     if (k >= max_it) break;
     T* pold = (k & 1) ? p1 : p0;
@@ -518,15 +543,16 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
     nprev = launch_cg_update(c, g, op2);
     prev = partsB;
     nred_prev = 1;
-    if ((k + 1) % check_every == 0) {
+    if (poll.due(k)) {
       HIPC(c, hipMemcpyAsync(c->pin, st, sizeof(CGState), hipMemcpyDeviceToHost, c->stream));
       sync(c);
       const CGState* sp = (CGState*)c->pin;
       harvest(sp->done ? sp->iter : k + 1);
       if (sp->done) break;
+      const double rr = sp->rrh[sp->iter & 1];
+      poll.update(k, rr, sp->thresh);
       if (stop_on_stagnation) {
         // rounding-limited (FP32) solve: give up when r.r has not halved in 256 iterations
-        const double rr = sp->rrh[sp->iter & 1];
         if (rr < 0.5 * best_rr) {
           best_rr = rr;
           best_k = k;
@@ -586,7 +612,10 @@ PoissonStats poisson(alofdft_ctx* c, const Geom& g, int fdn, double h, int preci
     // holds); a rounding breakdown (verdict 4) also restarts from the current iterate
     const bool pipe = cg_schedule_for(c, g, true) == 2;
     for (int restart = 0; restart < 8; ++restart) {
-      CGResult r = cg_solve<double>(c, g, A64, rhs, x, tol, max_cg - ps.iters, check_every, "cg64");
+      // a restart after a converged pipelined solve is expected to stop at once: poll after
+      // its first launch
+      CGResult r = cg_solve<double>(c, g, A64, rhs, x, tol, max_cg - ps.iters, check_every, "cg64", true, nullptr,
+                                    0, false, restart > 0 ? 1 : check_every);
       ps.iters += r.iters;
       ps.mv64 += r.iters + 1 + r.extra_mv;
       ps.relres = r.relres;
