@@ -267,7 +267,6 @@ def methods_mode():
     Lagrangian against the penalty method (eta fixed at 0) on the single atom and the 32-atom
     cluster, and the augmented Lagrangian's sensitivity to eta0, mu0 and kappa on the single
     atom -- stencil applications (the paper's cost measure), iterations, energy, time.  FP64."""
-    import numpy as np  # noqa: F401
     import torch
 
     import paper_1405_6456_amd as lib

@@ -60,7 +60,7 @@ def test_relax_of_a_relaxed_geometry_takes_no_step(C):
     assert np.abs(again["R"] - out["R"]).max() == 0.0
 
 
-def test_relax_step_cap_and_box_edge(C):
+def test_relax_step_cap_and_invalid_parameters(C):
     import paper_1405_6456_amd as lib
 
     S = pair(4.0)
