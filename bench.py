@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--cg-schedule", type=int, default=-1, choices=[-1, 0, 1, 2],
                     help="CG launches per iteration: 0/1 two launches, 2 pipelined (one launch, FP64 only), "
                          "-1 the library's automatic choice")
-    ap.add_argument("--mode", default="solve", choices=["solve", "stencil", "counters", "serve", "relax", "methods"],
+    ap.add_argument("--mode", default="solve", choices=["solve", "stencil", "counters", "serve", "relax", "methods", "large"],
                     help="stencil: only the streaming stencil measurement; counters: a short refined "
                          "Poisson solve and a reference copy (for counter passes); serve: the request "
                          "stream of fcc 1-3 clusters through the serving loop")
@@ -299,6 +299,54 @@ def methods_mode():
     ctx.close()
 
 
+def large_mode():
+    """The size of the paper's largest cluster on one device: 29^3 fcc cells (97 556 atoms),
+    474^3 = 106.5 M nodes.  A full ground state there takes hours, so this times its hot step:
+    the pseudocharge of all atoms, and Poisson solves (multipole boundary values, tolerance
+    1e-10, from a zero guess) of the charge u0^2 + b with the atomic-density guess, in FP64 and
+    FP32-refined, with the CG kernel's roofline fraction; and the plain stencil at that size."""
+    import torch
+
+    import paper_1405_6456_amd as lib
+    from paper_1405_6456_amd import synth
+
+    S = synth.config("fcc29")
+    g = S.grid
+    ctx = lib.Context(0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    b, _ = ctx.pseudocharge(S)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t
+    print(json.dumps({"mode": "large", "step": "pseudocharge", "atoms": S.M, "nodes": g.npts, "ms": round(1e3 * t_b, 1),
+                      "neutrality": float(g.h ** 3 * b.sum().item() + S.Z.sum())}), flush=True)
+    u0 = torch.from_numpy(synth.atomic_guess(S)).to("cuda:0")
+    rho = (u0 * u0 + b).contiguous()
+    del u0
+    for prec, name, es, per_node in ((lib.FP64, "f64", 8, 5), (lib.FP32_REFINED, "f32r", 4, 5)):
+        ctx.profile_cg_kernel(64)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        phi, its, rel = ctx.poisson(rho, g, bc=lib.BC_MULTIPOLE, precision=prec, tol=1e-10)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        n_t, ms, pts, sched = ctx.cg_kernel_stats(0 if prec == lib.FP64 else 1)
+        ctx.profile_cg_kernel(0)
+        alg = (12 if sched == 2 else 5) * es * g.npts
+        print(json.dumps({"mode": "large", "step": f"poisson_{name}", "cg_iters": its, "relres": rel,
+                          "wall_s": round(wall, 3), "us_per_iter": round(1e6 * wall / max(1, its), 1),
+                          "gpts": round(its * g.npts / wall / 1e9, 1), "cg_kernel_schedule": sched,
+                          "cg_kernel_ms": round(ms, 4),
+                          "cg_kernel_hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ms > 0 else None}),
+              flush=True)
+        del phi
+    for dt, name, es in ((0, "f64", 8), (1, "f32", 4)):
+        ms = ctx.bench_stencil(g.n, 6, dt, reps=10, nbuf=2)
+        print(json.dumps({"mode": "large", "step": f"stencil_{name}", "gpts": round(g.npts / (ms * 1e-3) / 1e9, 1),
+                          "hbm_frac": round(g.npts * 2 * es / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}), flush=True)
+    ctx.close()
+
+
 def relax_mode():
     """Relaxation of the two-atom analogue of the paper's Al2 case (Z = 3, Gaussian
     pseudocharges, 27^3 nodes at h = 0.9 Bohr) from 4.0 Bohr apart to ftol = 2e-4 Ha/Bohr:
@@ -380,6 +428,8 @@ def main():
         return relax_mode()
     if args.mode == "methods":
         return methods_mode()
+    if args.mode == "large":
+        return large_mode()
     S = synth.config(args.workload)
     if args.mode == "counters":
         return counters_mode(S, args.cg_schedule, args.precision)

@@ -340,6 +340,13 @@ struct PollPlan {
   }
 };
 
+// Iterations without r.r halving after which a rounding-limited (FP32) solve stops:
+// CG on the Laplacian can plateau for a number of iterations that grows with the grid's
+// longest side, so the window does too (256 up to 128 nodes per side).
+long long stall_window(const Geom& g) {
+  return std::max(256LL, 2LL * std::max(g.nx, std::max(g.ny, g.nz)));
+}
+
 // Whether CG launch k carries timing events: every prof_every-th launch, offset from
 // the host's polls of the solve state (every check_every launches), after which the
 // device has drained and the next launch starts cold.
@@ -440,7 +447,7 @@ CGResult cg_solve_pipe(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, cons
         if (rr < 0.5 * best_rr) {
           best_rr = rr;
           best_k = k;
-        } else if (k - best_k >= 256) {
+        } else if (k - best_k >= stall_window(g)) {
           ++k;
           break;
         }
@@ -552,11 +559,11 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
       const double rr = sp->rrh[sp->iter & 1];
       poll.update(k, rr, sp->thresh);
       if (stop_on_stagnation) {
-        // rounding-limited (FP32) solve: give up when r.r has not halved in 256 iterations
+        // rounding-limited (FP32) solve: give up when r.r has not halved within the window
         if (rr < 0.5 * best_rr) {
           best_rr = rr;
           best_k = k;
-        } else if (k - best_k >= 256) {
+        } else if (k - best_k >= stall_window(g)) {
           ++k;
           break;
         }
@@ -589,7 +596,7 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
     res.relres = 0.0;
     return res;
   }
-  res.iters = s.done ? s.iter : max_it;
+  res.iters = s.done ? s.iter : k;  // iterations run (the cap, or fewer after a stagnation stop)
   const double rr = s.done ? s.rr_last : s.rrh[(s.iter) & 1];
   res.relres = s.rhs2 > 0 ? std::sqrt(rr / s.rhs2) : 0.0;
   return res;

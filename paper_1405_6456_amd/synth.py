@@ -183,6 +183,8 @@ def config(name: str) -> System:
     fcc2     2^3 cells, 32 atoms,  63^3 nodes, h = 0.5, displacement seed 1405+2
     fcc5     5^3 cells, 500 atoms, 109^3 nodes, seed 1405+3
     fcc10    10^3 cells, 4000 atoms, 185^3 nodes, seed 1405+5
+    fcc29    29^3 cells, 97556 atoms, 474^3 nodes, seed 1405+29 (the size of the paper's
+             largest cluster, on one device)
     """
     if name == "single":
         return single_atom()
@@ -192,6 +194,8 @@ def config(name: str) -> System:
         return fcc_cluster(5, seed=1405 + 3, name=name)
     if name == "fcc10":
         return fcc_cluster(10, seed=1405 + 5, name=name)
+    if name == "fcc29":
+        return fcc_cluster(29, seed=1405 + 29, name=name)
     raise KeyError(name)
 
 

@@ -32,8 +32,9 @@ def test_uniform_guess_mean_and_noise():
 
 
 def test_workload_grids():
-    # box side m*a + 16 Bohr, n = round(L/h) + 1 at h = 0.5: 63^3, 109^3, 185^3 for m = 2, 5, 10
-    for name, m, n in (("fcc2", 2, 63), ("fcc5", 5, 109), ("fcc10", 10, 185)):
+    # box side m*a + 16 Bohr, n = round(L/h) + 1 at h = 0.5: 63^3, 109^3, 185^3, 474^3 for
+    # m = 2, 5, 10, 29
+    for name, m, n in (("fcc2", 2, 63), ("fcc5", 5, 109), ("fcc10", 10, 185), ("fcc29", 29, 474)):
         S = synth.config(name)
         assert S.grid.n == (n, n, n) and S.M == 4 * m ** 3 and S.N == 3 * S.M
         assert np.all(S.R >= np.array(S.grid.origin) + 7.0)
