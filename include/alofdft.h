@@ -268,12 +268,14 @@ int alofdft_bench_stencil(alofdft_ctx* ctx, const int n[3], int fd_half_width, i
  *       10 (2,8,1).
  *   11..16  forward-accumulating kernel (order 12): 11 (4,2,1), 12 (4,4,1),
  *       13 (4,2,2), 14 (8,2,1), 15 (4,4,2), 16 (8,4,1).
- *   100 + v  variant v with every z chunk swept upwards (v in 5..16; by default
+ *   100 + v  variant v with every z chunk swept upwards (v in 5..17; by default
  *       odd chunks are swept downwards).
+ *   17  CG kernels only: streaming kernel (8,1,1); other passes take their
+ *       automatic shape.
  * The stencil launches of the CG iterations (schedules 1 and 2 of
- * alofdft_set_cg_schedule) take variants 5, 6, 7, 9, 10 and 11..16 as above; every
- * other value selects their automatic shape, (8,2,1) for the pipelined iteration
- * and (4,2,1) for schedule 1.
+ * alofdft_set_cg_schedule) take variants 5, 6, 7, 9, 10, 11..16 and 17 as above;
+ * every other value selects their automatic shape, (8,2,1) for the pipelined
+ * iteration and (4,2,1) for schedule 1.
  * target_blocks is the number of stencil workgroups to aim for (it sets the z
  * chunk length); 0 fills one round of the workgroups the device holds at once.
  * inner_tol_exp is the FP32 inner-solve residual reduction 10^-inner_tol_exp of

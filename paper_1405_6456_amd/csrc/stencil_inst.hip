@@ -147,6 +147,7 @@ hipError_t launch_stencil_r(const LaunchCfg& lc, const Geom& g, const StencilW<T
         case 7: return launch_cfg2<T, R, 4, 2, 3, Op>(lc, g, W, op, nblocks, alt);
         case 9: return launch_cfg2<T, R, 8, 2, 1, Op>(lc, g, W, op, nblocks, alt);
         case 10: return launch_cfg2<T, R, 2, 8, 1, Op>(lc, g, W, op, nblocks, alt);
+        case 17: return launch_cfg2<T, R, 8, 1, 1, Op>(lc, g, W, op, nblocks, alt);
         default: break;
       }
     }

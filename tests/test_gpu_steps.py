@@ -130,7 +130,8 @@ def test_poisson_matches_oracle(C, orc, bc, precision, schedule):
     assert np.abs(phi.cpu().numpy() - ref).max() <= 1e-8 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("schedule,tuning", [(2, 5), (2, 6), (2, 7), (2, 9), (2, 10), (1, 6), (1, 9), (1, 10)])
+@pytest.mark.parametrize("schedule,tuning", [(2, 5), (2, 6), (2, 7), (2, 9), (2, 10), (2, 17), (1, 6), (1, 9),
+                                             (1, 10), (1, 17)])
 def test_poisson_cg_tile_variants(C, orc, schedule, tuning):
     # the CG kernels in every tile shape reach the oracle's solution (ragged 41x38x35 grid)
     g = synth.Grid((41, 38, 35), 0.45, (-9.0, -8.3, -7.6))
