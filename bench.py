@@ -62,10 +62,12 @@ def parse():
     return ap.parse_args()
 
 
-def traffic_for(kernel_key):
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def traffic_for(kernel_key, path=TRAFFIC_JSON):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -87,15 +89,16 @@ def kernel_digest():
     return h.hexdigest()[:16]
 
 
-def summarize_counters(fetch_csv, write_csv, key):
+def summarize_counters(fetch_csv, write_csv, key, path=TRAFFIC_JSON):
     """HBM bytes per launch of the CG stencil kernel from a FETCH_SIZE pass and a WRITE_SIZE
     pass (KiB per dispatch) of --mode counters, each scaled by what the same counter reads for
-    the reference copy of 256 MiB in that run.  Updates profiles/traffic.json[key]."""
+    the reference copy of 256 MiB in that run.  Updates the summary file (profiles/traffic.json)
+    at key."""
     import csv
 
-    def per_kernel(path, counter):
+    def per_kernel(csv_path, counter):
         out = {}
-        with open(path) as f:
+        with open(csv_path) as f:
             for r in csv.DictReader(f):
                 if r["Counter_Name"] != counter:
                     continue
@@ -104,20 +107,19 @@ def summarize_counters(fetch_csv, write_csv, key):
 
     copy_bytes = 256 * 1024 * 1024
     res = {}
-    for path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
-        pk = per_kernel(path, counter)
+    for csv_path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
+        pk = per_kernel(csv_path, counter)
         name = "CGPipeOp<double>" if key.startswith("cgpipe") else "CGP1LOp<float>"
         cg = [v for k, vs in pk.items() if name in k and "k_stencil" in k for v in vs]
         cp = [v for k, vs in pk.items() if "elementwise" in k or "copy" in k.lower() for v in vs]
         cp = [v for v in cp if v > 0.5 * max(cp)] if cp else []
         if not cg or not cp:
-            raise SystemExit(f"{path}: no CG stencil or copy dispatches with {counter}")
+            raise SystemExit(f"{csv_path}: no CG stencil or copy dispatches with {counter}")
         kib_cg = sum(cg) / len(cg)
         kib_copy = sum(cp) / len(cp)
         scale = copy_bytes / (kib_copy * 1024.0)
         res[counter] = {"kib_per_dispatch": round(kib_cg, 1), "copy_kib": round(kib_copy, 1),
                         "scale": round(scale, 4), "bytes": round(kib_cg * 1024.0 * scale)}
-    path = os.path.join(ROOT, "profiles", "traffic.json")
     data = json.load(open(path)) if os.path.exists(path) else {}
     data[key] = {"kernels_sha256_16": kernel_digest(),
                  "bytes_per_launch": res["FETCH_SIZE"]["bytes"] + res["WRITE_SIZE"]["bytes"],

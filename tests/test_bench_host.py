@@ -1,0 +1,49 @@
+"""Host logic of bench.py (no GPU): the one-GPU refusal, the HBM-counter summary and its
+source-hash gate."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def _csv(path, rows):
+    with open(path, "w") as f:
+        f.write("Kernel_Name,Counter_Name,Counter_Value\n")
+        for k, c, v in rows:
+            f.write(f'"{k}",{c},{v}\n')
+
+
+def test_counter_summary_scales_by_the_reference_copy(tmp_path):
+    # the copy of 256 MiB reads 131072 KiB on FETCH_SIZE (factor 2) and 262144 KiB on
+    # WRITE_SIZE (factor 1); the CG kernel's per-dispatch mean is scaled by the same factor
+    kern = "void alofdft::k_stencil2<float, 6, 4, 2, 1, alofdft::CGP1LOp<float> >(alofdft::Geom)"
+    fetch, write = tmp_path / "f.csv", tmp_path / "w.csv"
+    _csv(fetch, [(kern, "FETCH_SIZE", 1000.0), (kern, "FETCH_SIZE", 1200.0),
+                 ("elementwise_kernel copy", "FETCH_SIZE", 131072.0), ("tiny copy", "FETCH_SIZE", 1.0)])
+    _csv(write, [(kern, "WRITE_SIZE", 500.0), ("elementwise_kernel copy", "WRITE_SIZE", 262144.0)])
+    out = tmp_path / "traffic.json"
+    bench.summarize_counters(str(fetch), str(write), "cg_stencil_f32_test", path=str(out))
+    ent = json.load(open(out))["cg_stencil_f32_test"]
+    assert ent["read_bytes"] == round(1100.0 * 1024 * 2.0)
+    assert ent["write_bytes"] == round(500.0 * 1024 * 1.0)
+    assert ent["bytes_per_launch"] == ent["read_bytes"] + ent["write_bytes"]
+    assert ent["kernels_sha256_16"] == bench.kernel_digest()
+    # the gate: the bytes are reported only while the kernel sources match
+    assert bench.traffic_for("cg_stencil_f32_test", path=str(out)) == ent["bytes_per_launch"]
+    data = json.load(open(out))
+    data["cg_stencil_f32_test"]["kernels_sha256_16"] = "0" * 16
+    json.dump(data, open(out, "w"))
+    assert bench.traffic_for("cg_stencil_f32_test", path=str(out)) is None
+    assert bench.traffic_for("absent", path=str(out)) is None
+
