@@ -88,7 +88,7 @@ typedef struct {
   int max_secant;         /* secant steps per line search (4) */
   double secant_rel;      /* line-search slope reduction (0.1) */
   int restart_every;      /* nonlinear CG restart period (50) */
-  int cg_check_every;     /* most CG iterations between host convergence checks (16); the
+  int cg_check_every;     /* most CG iterations between host convergence checks (32); the
                              checks are timed by the observed residual reduction */
   uint64_t seed;          /* seed of the default initial guess (6456) */
 } alofdft_params;

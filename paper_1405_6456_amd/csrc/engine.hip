@@ -340,6 +340,9 @@ struct PollPlan {
   }
 };
 
+// Default of the most CG launches between two host reads of a solve's state.
+constexpr int kCheckEvery = 32;
+
 // Iterations without r.r halving after which a rounding-limited (FP32) solve stops:
 // CG on the Laplacian can plateau for a number of iterations that grows with the grid's
 // longest side, so the window does too (256 up to 128 nodes per side).
@@ -1596,7 +1599,7 @@ int alofdft_default_params(alofdft_params* p) {
   p->max_secant = 4;
   p->secant_rel = 0.1;
   p->restart_every = 50;
-  p->cg_check_every = 16;
+  p->cg_check_every = kCheckEvery;
   p->seed = 6456;
   return ALOFDFT_OK;
 }
@@ -1778,7 +1781,7 @@ int alofdft_poisson(alofdft_ctx* c, const int n[3], double h, const double origi
     RhsOp<double> rop{v, b, rhs, bc == ALOFDFT_BC_MULTIPOLE ? mom : nullptr, stencil_weights<double>(fdn, h, 1.0),
                       fdn, n[0], n[1], n[2], f, nullptr};
     launch_pw(c, g, rop);
-    PoissonStats ps = poisson(c, g, fdn, h, precision, rhs, x, tol, max_cg, 16);
+    PoissonStats ps = poisson(c, g, fdn, h, precision, rhs, x, tol, max_cg, kCheckEvery);
     unpack<double, double>(c, g, x, phi);
     sync(c);
     if (iters) *iters = ps.iters;
