@@ -276,7 +276,7 @@ def methods_mode():
 
     ctx = lib.Context(0)
 
-    def run(name, **kw):
+    def run(name, quiet=False, **kw):
         S = synth.config(name)
         u0 = synth.initial_u(S.grid, S.N) if name == "single" else synth.atomic_guess(S)
         u0d = torch.from_numpy(u0).to("cuda:0").contiguous()
@@ -288,10 +288,11 @@ def methods_mode():
         line = {"mode": "methods", "workload": name, **kw, "status": o["status"], "matvecs": o["matvec_fp64"],
                 "outer": o["outer"], "inner": o["inner"], "E_per_atom": o["E_total"] / S.M, "eta_star": o["eta_star"],
                 "C_h_per_N": o["C_h"] / S.N, "wall_s": round(wall, 3)}
-        print(json.dumps(line), flush=True)
+        if not quiet:
+            print(json.dumps(line), flush=True)
         return o
 
-    run("single")  # warm-up
+    run("single", quiet=True)  # warm-up
     for name in ("single", "fcc2"):
         for method in (lib.AL, lib.PENALTY):
             run(name, method=method)
