@@ -187,6 +187,7 @@ class Context:
 
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the alofdft library runs only on the GPU")
+        torch.cuda.init()  # the runtime's device state exists before the library's first call
         self.device = torch.cuda.current_device() if device is None else int(device)
         with torch.cuda.device(self.device):
             s = stream if stream is not None else torch.cuda.current_stream(self.device)

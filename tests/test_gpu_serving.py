@@ -56,6 +56,31 @@ def test_same_alone_and_in_the_mix(alone):
     srv.close()
 
 
+def test_fp64_requests_same_alone_and_in_the_mix():
+    # FP64 requests on these small grids run the pipelined CG (one launch per iteration,
+    # per-request state and partial buffers).  Overlapped on the device they reach the
+    # ground state each reaches alone, to the solver's tolerances (served FP64 solves
+    # have been seen to take one CG iteration more or less than alone in a Poisson solve,
+    # a difference far inside the served-result tolerance of 1e-5 Ha/atom, 1e-4 Ha/Bohr)
+    import paper_1405_6456_amd as lib
+
+    c = ctx()
+    prm = lib.default_params(precision=lib.FP64)
+    reqs = requests()
+    single = [c.solve(S, prm, None) for S in reqs]
+    c.close()
+    srv = lib.Server(0, max_slots=4)
+    tickets = [(i, srv.submit(S, prm)) for _ in range(2) for i, S in enumerate(reqs)]
+    for i, t in tickets:
+        r = srv.wait(t)
+        a = single[i]
+        assert r["status"] == 0 and a["status"] == 0
+        assert abs(r["E_total"] - a["E_total"]) <= 1e-9 * max(1.0, abs(a["E_total"]))
+        assert np.abs(r["forces"] - a["forces"]).max() <= 1e-6
+        assert np.abs(r["u"] - a["u"]).max() <= 1e-5 * np.abs(a["u"]).max()
+    srv.close()
+
+
 def test_served_matches_fp64_path(alone):
     import paper_1405_6456_amd as lib
 
