@@ -41,7 +41,8 @@ class OrParams(C.Structure):
                 ("tol_poisson", C.c_double), ("bc", C.c_int), ("max_al", C.c_int), ("max_nlcg", C.c_int),
                 ("max_cg", C.c_int), ("sigma0", C.c_double), ("max_secant", C.c_int),
                 ("secant_rel", C.c_double), ("restart_every", C.c_int), ("tf_on", C.c_int),
-                ("hartree_on", C.c_int), ("vext", C.POINTER(C.c_double)), ("verbose", C.c_int)]
+                ("hartree_on", C.c_int), ("vext", C.POINTER(C.c_double)), ("verbose", C.c_int),
+                ("al_stop", C.c_int), ("tol_energy", C.c_double), ("pseudo", C.c_int)]
 
 
 class OrResult(C.Structure):
@@ -75,12 +76,19 @@ def lib():
         L.or_bJ.argtypes = [C.c_double] * 4
         L.or_VJ.restype = C.c_double
         L.or_VJ.argtypes = [C.c_double] * 3
-        L.or_pseudocharge.argtypes = [C.POINTER(OrGrid), C.c_int, _DP, _DP, C.c_double, C.c_double, _DP]
+        L.or_pseudocharge.argtypes = [C.POINTER(OrGrid), C.c_int, _DP, _DP, C.c_double, C.c_double, C.c_int,
+                                      C.c_int, _DP]
         L.or_pseudocharge_at.restype = C.c_double
         L.or_pseudocharge_at.argtypes = [C.POINTER(OrGrid), C.c_int, _DP, _DP, C.c_double, C.c_double,
-                                         C.c_int, C.c_int, C.c_int]
+                                         C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
         L.or_self_energy.restype = C.c_double
-        L.or_self_energy.argtypes = [C.POINTER(OrGrid), C.c_int, _DP, _DP, C.c_double, C.c_double]
+        L.or_self_energy.argtypes = [C.POINTER(OrGrid), C.c_int, _DP, _DP, C.c_double, C.c_double, C.c_int,
+                                     C.c_int]
+        L.or_bJ_fd.restype = C.c_double
+        L.or_bJ_fd.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, C.c_double, C.c_double,
+                               C.c_double]
+        L.or_atomic_guess.argtypes = [C.POINTER(OrGrid), C.c_int, _DP, _DP, C.c_double, C.c_double, C.c_double,
+                                      _DP]
         L.or_overlap_correction.restype = C.c_double
         L.or_overlap_correction.argtypes = [C.c_int, _DP, _DP, C.c_double, _DP]
         L.or_moments.argtypes = [C.POINTER(OrGrid), _DP, _DP]
@@ -199,21 +207,36 @@ def VJ(Z, s, r) -> float:
     return lib().or_VJ(Z, s, r)
 
 
-def pseudocharge(system, s=1.0, rc=7.0) -> np.ndarray:
+def pseudocharge(system, s=1.0, rc=7.0, mode=0, fd_n=6) -> np.ndarray:
+    """b on the grid: mode 0 Gaussian b_J, mode 1 -(1/4 pi) Delta_h V_J (order 2 fd_n)."""
     S = Sys(system)
     b = np.zeros(system.grid.shape)
-    lib().or_pseudocharge(C.byref(S.s.grid), S.s.M, S.s.R, S.s.Z, s, rc, _p(b))
+    lib().or_pseudocharge(C.byref(S.s.grid), S.s.M, S.s.R, S.s.Z, s, rc, mode, fd_n, _p(b))
     return b
 
 
-def pseudocharge_at(system, i, j, k, s=1.0, rc=7.0) -> float:
+def pseudocharge_at(system, i, j, k, s=1.0, rc=7.0, mode=0, fd_n=6) -> float:
     S = Sys(system)
-    return lib().or_pseudocharge_at(C.byref(S.s.grid), S.s.M, S.s.R, S.s.Z, s, rc, i, j, k)
+    return lib().or_pseudocharge_at(C.byref(S.s.grid), S.s.M, S.s.R, S.s.Z, s, rc, mode, fd_n, i, j, k)
 
 
-def self_energy(system, s=1.0, rc=7.0) -> float:
+def self_energy(system, s=1.0, rc=7.0, mode=0, fd_n=6) -> float:
     S = Sys(system)
-    return lib().or_self_energy(C.byref(S.s.grid), S.s.M, S.s.R, S.s.Z, s, rc)
+    return lib().or_self_energy(C.byref(S.s.grid), S.s.M, S.s.R, S.s.Z, s, rc, mode, fd_n)
+
+
+def bJ_fd(Z, s, rc, h, fd_n, dx, dy, dz) -> float:
+    """-(1/4 pi) Delta_h V_J at offset (dx, dy, dz) from the nucleus (0 beyond rc)."""
+    return lib().or_bJ_fd(Z, s, rc, h, fd_n, dx, dy, dz)
+
+
+def atomic_guess(system, width=1.5, floor=1e-3) -> np.ndarray:
+    """Superposition of one Gaussian of Z_J electrons per atom (width w, cut at 5w) plus
+    floor x N/V, scaled to h^3 sum u^2 = N; returns u0 = sqrt(rho)."""
+    S = Sys(system)
+    u = np.zeros(system.grid.shape)
+    lib().or_atomic_guess(C.byref(S.s.grid), S.s.M, S.s.R, S.s.Z, float(system.N), width, floor, _p(u))
+    return u
 
 
 def overlap_correction(system, s=1.0):

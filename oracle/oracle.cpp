@@ -64,6 +64,9 @@ typedef struct {
   int hartree_on;       // test switch: electrostatics (pseudocharge + Hartree)
   const double* vext;   // test switch: fixed external potential on the grid (nullable)
   int verbose;
+  int al_stop;          // outer stopping rule: 0 = |C_h|/N < tol_constraint, 1 = |E_q - E_(q-1)|/M < tol_energy
+  double tol_energy;    // Ha per atom (rule 1)
+  int pseudo;           // pseudocharge: 0 = Gaussian b_J, 1 = -(1/4 pi) Delta_h V_J at the nodes
 } OrParams;
 
 typedef struct {
@@ -215,6 +218,32 @@ double or_VJ(double Z, double s, double r) {
   return -Z * std::erf(r / s) / r;
 }
 
+// reading: the paper builds b_J = -(1/4 pi) Delta_h V_J from the pseudopotential on
+// the nodes of the ball (Sec. 4, the b_J formula after Eq. FD:Laplacian); here V_J is the
+// Gaussian potential above, and b_J is taken on the same ball |x - R_J| <= r_cut (beyond it
+// V_J is the Coulomb potential to 1e-21 and its discrete Laplacian only the truncation
+// error of the stencil).  (dx, dy, dz) = x - R_J.
+double or_bJ_fd(double Z, double s, double rcut, double h, int n, double dx, double dy, double dz) {
+  if (dx * dx + dy * dy + dz * dz > rcut * rcut) return 0.0;
+  std::vector<double> w(n + 1);
+  or_fd_weights(n, h, w.data());
+  auto V = [&](double x, double y, double z) { return or_VJ(Z, s, std::sqrt(x * x + y * y + z * z)); };
+  double lap = 0.0;
+  for (int p = 0; p <= n; ++p) {
+    double ph = p * h;
+    lap += w[p] * (V(dx + ph, dy, dz) + V(dx - ph, dy, dz) + V(dx, dy + ph, dz) + V(dx, dy - ph, dz) +
+                   V(dx, dy, dz + ph) + V(dx, dy, dz - ph));
+  }
+  return -lap / (4.0 * M_PI);
+}
+
+// b_J at offset (dx, dy, dz) from its nucleus for pseudocharge mode 0 (Gaussian) or 1
+// (discrete Laplacian of V_J).
+static double bJ_mode(int mode, int n, double h, double Z, double s, double rcut, double dx, double dy, double dz) {
+  if (mode == 1) return or_bJ_fd(Z, s, rcut, h, n, dx, dy, dz);
+  return or_bJ(Z, s, rcut, std::sqrt(dx * dx + dy * dy + dz * dz));
+}
+
 // Index box of the nodes that can lie within distance rad of point x.
 static void ball_box(const OrGrid* g, const double* x, double rad, int lo[3], int hi[3]) {
   for (int a = 0; a < 3; ++a) {
@@ -226,8 +255,8 @@ static void ball_box(const OrGrid* g, const double* x, double rad, int lo[3], in
 }
 
 // b = sum_J b_J on the grid, visiting each atom's ball (Sec. 4, construction of b).
-void or_pseudocharge(const OrGrid* g, int M, const double* R, const double* Z, double s, double rcut,
-                     double* b) {
+void or_pseudocharge(const OrGrid* g, int M, const double* R, const double* Z, double s, double rcut, int mode,
+                     int n, double* b) {
   std::memset(b, 0, sizeof(double) * npts(g));
   for (int J = 0; J < M; ++J) {
     int lo[3], hi[3];
@@ -239,27 +268,28 @@ void or_pseudocharge(const OrGrid* g, int M, const double* R, const double* Z, d
           pos(g, i, j, k, x);
           double dx = x[0] - R[3 * J], dy = x[1] - R[3 * J + 1], dz = x[2] - R[3 * J + 2];
           double r = std::sqrt(dx * dx + dy * dy + dz * dz);
-          if (r <= rcut) b[lin(g, i, j, k)] += or_bJ(Z[J], s, rcut, r);
+          if (r <= rcut) b[lin(g, i, j, k)] += bJ_mode(mode, n, g->h, Z[J], s, rcut, dx, dy, dz);
         }
   }
 }
 
 // b at one node, summing over all atoms (used for sampled checks on large grids).
 double or_pseudocharge_at(const OrGrid* g, int M, const double* R, const double* Z, double s,
-                          double rcut, int i, int j, int k) {
+                          double rcut, int mode, int n, int i, int j, int k) {
   double x[3], acc = 0.0;
   pos(g, i, j, k, x);
   for (int J = 0; J < M; ++J) {
     double dx = x[0] - R[3 * J], dy = x[1] - R[3 * J + 1], dz = x[2] - R[3 * J + 2];
     double r = std::sqrt(dx * dx + dy * dy + dz * dz);
-    if (r <= rcut) acc += or_bJ(Z[J], s, rcut, r);
+    if (r <= rcut) acc += bJ_mode(mode, n, g->h, Z[J], s, rcut, dx, dy, dz);
   }
   return acc;
 }
 
 // Self energy 1/2 sum_J int b_J V_J with the nodal quadrature (Sec. 2, last term
 // of Eq. ElectroststaticReformulation; Sec. 4 quadrature).
-double or_self_energy(const OrGrid* g, int M, const double* R, const double* Z, double s, double rcut) {
+double or_self_energy(const OrGrid* g, int M, const double* R, const double* Z, double s, double rcut, int mode,
+                      int n) {
   double h3 = g->h * g->h * g->h, tot = 0.0;
   for (int J = 0; J < M; ++J) {
     int lo[3], hi[3];
@@ -272,11 +302,43 @@ double or_self_energy(const OrGrid* g, int M, const double* R, const double* Z, 
           pos(g, i, j, k, x);
           double dx = x[0] - R[3 * J], dy = x[1] - R[3 * J + 1], dz = x[2] - R[3 * J + 2];
           double r = std::sqrt(dx * dx + dy * dy + dz * dz);
-          if (r <= rcut) acc += or_bJ(Z[J], s, rcut, r) * or_VJ(Z[J], s, r);
+          if (r <= rcut) acc += bJ_mode(mode, n, g->h, Z[J], s, rcut, dx, dy, dz) * or_VJ(Z[J], s, r);
         }
     tot += 0.5 * h3 * acc;
   }
   return tot;
+}
+
+// Initial guess (Sec. 4: a superposition of isolated-atom densities).  reading: each
+// atom contributes a Gaussian density of Z_J electrons, rho_J = Z_J (pi w^2)^(-3/2)
+// exp(-r^2/w^2) cut at r = 5w, and a uniform floor of floor_frac N/V keeps u > 0 in the
+// vacuum; the sum is scaled to h^3 sum rho = N and u0 = sqrt(rho).
+void or_atomic_guess(const OrGrid* g, int M, const double* R, const double* Z, double N, double w,
+                     double floor_frac, double* u) {
+  const long n = npts(g);
+  const double h3 = g->h * g->h * g->h, rc = 5.0 * w, norm = std::pow(M_PI * w * w, -1.5);
+  std::vector<double> rho(n, 0.0);
+  for (int J = 0; J < M; ++J) {
+    int lo[3], hi[3];
+    ball_box(g, R + 3 * J, rc, lo, hi);
+    for (int k = lo[2]; k <= hi[2]; ++k)
+      for (int j = lo[1]; j <= hi[1]; ++j)
+        for (int i = lo[0]; i <= hi[0]; ++i) {
+          double x[3];
+          pos(g, i, j, k, x);
+          double dx = x[0] - R[3 * J], dy = x[1] - R[3 * J + 1], dz = x[2] - R[3 * J + 2];
+          double r2 = dx * dx + dy * dy + dz * dz;
+          if (r2 <= rc * rc) rho[lin(g, i, j, k)] += Z[J] * norm * std::exp(-r2 / (w * w));
+        }
+  }
+  double tot = 0.0;
+  const double fl = floor_frac * N / (n * h3);
+  for (long i = 0; i < n; ++i) {
+    rho[i] += fl;
+    tot += rho[i];
+  }
+  const double scale = N / (h3 * tot);
+  for (long i = 0; i < n; ++i) u[i] = std::sqrt(rho[i] * scale);
 }
 
 // Overlap correction (Appendix A).  reading: for Gaussian pseudocharges the
@@ -450,8 +512,10 @@ static void work_init(Work& W, const OrSystem* sys, const OrParams* prm) {
   W.E_self = 0.0;
   W.E_c = 0.0;
   if (prm->hartree_on) {
-    or_pseudocharge(&sys->grid, sys->M, sys->R, sys->Z, prm->gauss_s, prm->r_cut, W.b.data());
-    W.E_self = or_self_energy(&sys->grid, sys->M, sys->R, sys->Z, prm->gauss_s, prm->r_cut);
+    or_pseudocharge(&sys->grid, sys->M, sys->R, sys->Z, prm->gauss_s, prm->r_cut, prm->pseudo, prm->fd_n,
+                    W.b.data());
+    W.E_self = or_self_energy(&sys->grid, sys->M, sys->R, sys->Z, prm->gauss_s, prm->r_cut, prm->pseudo,
+                              prm->fd_n);
     W.E_c = or_overlap_correction(sys->M, sys->R, sys->Z, prm->gauss_s, nullptr);
   }
   W.grad_evals = W.poisson_solves = W.cg_iters = W.matvecs = 0;
@@ -865,7 +929,7 @@ void or_forces(const OrSystem* sys, const OrParams* prm, const double* phi, doub
       double x[3];
       pos(g, i, j, k, x);
       double dx = x[0] - RJ[0], dy = x[1] - RJ[1], dz = x[2] - RJ[2];
-      return or_bJ(ZJ, s, rc, std::sqrt(dx * dx + dy * dy + dz * dz));
+      return bJ_mode(prm->pseudo, n, h, ZJ, s, rc, dx, dy, dz);
     };
     int lo[3], hi[3];
     ball_box(g, RJ, rc, lo, hi);
@@ -918,6 +982,9 @@ void or_default_params(OrParams* p) {
   p->hartree_on = 1;
   p->vext = nullptr;
   p->verbose = 0;
+  p->al_stop = 0;
+  p->tol_energy = 3.6749e-6;  // 1e-4 eV per atom (Sec. 5.3.1), in Hartree
+  p->pseudo = 0;
 }
 
 // Ground state for fixed nuclei (Sec. 3, Algorithm AugLag, and Sec. 5.3.2 for
@@ -961,7 +1028,11 @@ int or_solve(const OrSystem* sys, const OrParams* prm, const double* u0, double*
         std::printf("  AL q=%d eta=%.10f mu=%.3e C/N=%.3e E=%.12f nlcg=%ld |g|=%.2e\n", q, eta, mu,
                     C / sys->N, e.E_total, its, gn);
       res->eta = eta_next;
-      if (std::fabs(C) / sys->N < prm->tol_constraint && st == 0) {
+      // Algorithm AugLag stops on the change of the energy between outer steps; the
+      // workloads' rule is the constraint (both need a converged inner problem)
+      const bool stop = prm->al_stop == 1 ? (q > 0 && std::fabs(res->dE_last) / sys->M < prm->tol_energy)
+                                          : std::fabs(C) / sys->N < prm->tol_constraint;
+      if (stop && st == 0) {
         status = 0;
         break;
       }
@@ -969,7 +1040,7 @@ int or_solve(const OrSystem* sys, const OrParams* prm, const double* u0, double*
       mu *= prm->kappa;
     }
   }
-  // final energies at the returned u with a fresh tight potential
+  // energies of the last evaluation of the returned u (phi solved to tol_poisson there)
   res->E_total = e.E_total;
   res->E_TF = e.E_TF;
   res->E_vW = e.E_vW;

@@ -3,8 +3,11 @@
 Calls only the CPU oracle (oracle/) and the input generators; nothing here touches
 the GPU library.  Usage: python tests/golden/make_golden.py single fcc2 [fcc5]
 Each fixture records the parameters it was made with, the energies, the multiplier,
-the constraint, the forces and, for small grids, u and phi at sampled nodes.
+the constraint, the forces, u and phi at sampled nodes, and a hash of the oracle source
+that wrote it (a test checks that it equals the hash of the current source, so a change
+of the oracle's arithmetic forces the fixtures to be written again).
 """
+import hashlib
 import json
 import os
 import sys
@@ -19,6 +22,12 @@ import oracle  # noqa: E402
 from paper_1405_6456_amd import synth  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def oracle_source_hash():
+    """sha256 (first 16 hex digits) of the oracle's C++ source."""
+    with open(os.path.join(ROOT, "oracle", "oracle.cpp"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def sample_nodes(grid, count=64, seed=99):
@@ -38,6 +47,7 @@ def make(name, method=0, threads=None):
     out = {
         "workload": name,
         "method": method,
+        "oracle_sha256_16": oracle_source_hash(),
         "params": {"fd_n": 6, "lambda": 0.2, "xc": "LDA_PZ", "gauss_s": 1.0, "r_cut": 7.0, "eta0": -0.2,
                    "mu0": 1.0, "kappa": 0.1, "tol_constraint": 1e-8, "tol_grad": 1e-6, "tol_poisson": 1e-10,
                    "bc": "multipole", "u0": "synth.initial_u seed 6456"},

@@ -133,16 +133,18 @@ def test_residual_is_half_derivative_of_L(orc):
 
 # ---------------------------------------------------------------- forces vs energy
 @pytest.mark.slow
-def test_forces_match_energy_difference(orc):
+@pytest.mark.parametrize("pseudo", [0, 1])
+def test_forces_match_energy_difference(orc, pseudo):
     # f_z on atom 0 against -dE/dz by a central difference of converged energies
     # (zero-Dirichlet phi, so the energy is exactly variational in phi).  The force
     # formula (App. A) takes the order-2n finite-difference gradient of the sampled
     # pseudocharge, not its exact derivative, so it matches the energy difference only
     # up to that gradient's error on the Gaussian: about 2e-4 Ha/Bohr at h = 0.75,
-    # 2e-5 at h = 0.6 (it falls like a high power of h).  Hence h = 0.6 here.
+    # 2e-5 at h = 0.6 (it falls like a high power of h).  Hence h = 0.6 here.  pseudo 1:
+    # the pseudocharge built as the discrete Laplacian of V_J (Sec. 4), same formula.
     d = 0.01
     h = 0.6
-    prm = orc.params(bc=0, tol_constraint=1e-10, tol_grad=1e-8, tol_poisson=1e-12)
+    prm = orc.params(bc=0, tol_constraint=1e-10, tol_grad=1e-8, tol_poisson=1e-12, pseudo=pseudo)
     base = pair_system(h=h)
     u0 = synth.initial_u(base.grid, base.N)
     r0 = orc.solve(base, prm, u0)

@@ -52,6 +52,28 @@ def test_branches_meet_at_rs_1(orc):
     assert abs(lo - hi) < 5e-5
 
 
+def test_correlation_slope_continuous_at_rs_1(orc):
+    # Perdew and Zunger fixed the high-density constants (A1, B1, C1, D1) so that the
+    # correlation energy and its first r_s derivative both join the low-density form
+    # continuously at r_s = 1.  The value continuity (test above) checks gamma1, B1 and
+    # D1; the slope continuity checks C1 on the high-density side and beta1, beta2
+    # separately on the low-density side (their roles in the slope differ: d/dr_s of
+    # beta1 sqrt(r_s) is beta1/2 at r_s = 1, of beta2 r_s it is beta2).
+    ex = lambda rs: -0.45816529328314287 / rs  # exchange, pinned above
+
+    def ec(rs):
+        return orc.xc_point(rs_to_u(rs))[0] - ex(rs)
+
+    d = 1e-4
+    left = (ec(1 - d) - ec(1 - 3 * d)) / (2 * d)   # slope at 1 - 2d, high-density branch
+    right = (ec(1 + 3 * d) - ec(1 + d)) / (2 * d)  # slope at 1 + 2d, low-density branch
+    # the one-sided slopes differ by the rounding of the printed constants (~1.3e-5) and
+    # by 2d times the curvature (~6e-6); a wrong C1, a sign of D1 or beta1 and beta2
+    # exchanged moves one side by more than 9e-3
+    assert abs(left - right) < 5e-5, (left, right)
+    assert left > 0 and right > 0
+
+
 def test_zero_density_limit(orc):
     assert orc.xc_point(0.0) == (0.0, 0.0)
     e, v = orc.xc_point(1e-16)  # rho = 1e-32, below the 1e-30 cut
