@@ -1,23 +1,33 @@
-"""Benchmark: one step = one full ground-state solve of a synthetic Al-like fcc cluster.
+"""Benchmark of the augmented Lagrangian OF-DFT hot path on one MI355X.
 
-Workload (default, fcc2): 2x2x2 conventional fcc cells, 32 atoms, a = 7.6 Bohr,
-seeded 0.1 Bohr displacements, 8 Bohr vacuum, h = 0.5 Bohr (63^3 nodes), order-12
-stencil, Gaussian pseudocharge (Z = 3, s = 1), TFW + LDA, AL outer loop (eta0 -0.2,
-mu0 1, kappa 0.1), tolerances 1e-8 / 1e-6 / 1e-10.  The timed path solves Poisson
-with FP32 stencil/CG vectors inside FP64 iterative refinement; the plain FP64 GPU
-path is timed once afterwards on the same input for the speedup and the error.
---workload fcc5 / fcc10 select the 500-atom (109^3) and 4000-atom (185^3) clusters.
+Default (--mode hotpath, --workload fcc10): the 4000-atom Al-like cluster (10^3 fcc cells,
+a = 7.6 Bohr, seeded 0.1 Bohr displacements, 8 Bohr vacuum, h = 0.5 Bohr: 185^3 nodes),
+order-12 stencil, Gaussian pseudocharges (Z = 3, s = 1), TFW + LDA, multipole boundary
+values, in the precision that configuration names: FP32 stencil and CG vectors inside an
+FP64 iterative-refinement Poisson solve.  One step is one pass of the whole hot path from
+the atomic-density guess already resident in HBM: the pseudocharge and self energy of the
+4000 nuclei, the density and its multipole moments, the boundary fold, the Poisson solve
+from zero to 1e-10, the residual and energy pass, two nonlinear-CG steps (each a line
+search whose trial points re-solve Poisson warm-started), the multiplier update and the
+Hellmann-Feynman forces (alofdft_solve_device with max_outer = 1, max_inner = 2).  The same
+pass in FP64 is timed afterwards for the speedup and the error of the refined path.
 
-Prints one JSON line.  value = stencil grid-point updates per second over the whole
-solve: (FP64 + FP32 stencil applications) x nodes / wall time of the timed steps.
-roofline: the first half of each CG iteration (stencil of r; p and A p updated by
-linearity; p.Ap), the dominant kernel, with its algorithmic bytes (read r, p and A p,
-write p and A p) over its mean kernel duration.
+The JSON line: value = stencil point updates per second over the timed steps (every stencil
+application of the pass, FP32 and FP64, times the nodes, over the wall time);
+stencil_streaming_185 = the plain stencil alone over six rotating buffer pairs (more than
+the 256 MB Infinity Cache) with 16 / 8 bytes per point; roofline = the dominant kernel pair,
+one FP32 CG iteration (the stencil launch and the x, r update launch), at 40 bytes per node
+(the algorithmic traffic of a fused CG iteration in FP32), over the mean kernel time of the
+sampled iterations (HIP events stamped by the runtime on both launches); cpu_baseline = the
+oracle's CG iterations on the same grid and right-hand side, all host threads and one.
 
-Other modes: --mode stencil (stencil throughput only), --mode counters (a short run
-of the refined Poisson solve for hardware-counter passes, followed by a reference
-copy of known size), --mode serve (the request stream through the serving loop),
---summarize-counters (writes profiles/traffic.json from counter CSVs).
+Other modes: ground_state (time to converged energy and forces, FP32-refined and FP64),
+stencil (plain stencil only, then a reference copy for counter calibration), counters (a
+short refined Poisson solve, then the reference copy), serve (the 64-request stream of fcc
+1-3 clusters at arrival rates 0.5, 1 and 2 times the sequential FP64 capacity), relax,
+methods (augmented Lagrangian, penalty and Lagrange multiplier, and the eta0 / mu0 / kappa
+sweep), large (the 97 556-atom cluster's hot steps), --summarize-counters (writes
+profiles/traffic.json from two counter CSVs of --mode counters).
 """
 import argparse
 import json
@@ -30,52 +40,51 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "Gpts/s stencil (%HBM peak); AL-OFDFT solves/s, p50/p99 latency vs FP64"
+# algorithmic bytes per node: a stencil application reads x once and writes y once; a fused
+# CG iteration makes about ten passes over arrays (read r, p, A p and write p, A p in the
+# first launch; read x, r, p, A p and write x, r in the second, counted as 4 + 6 arrays)
+STENCIL_BYTES = {8: 16, 4: 8}
+CG_ITER_BYTES = {8: 80, 4: 40}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="fcc2", choices=["single", "fcc2", "fcc5", "fcc10"])
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="fcc10", choices=["single", "fcc2", "fcc5", "fcc10"])
     ap.add_argument("--precision", default="auto", choices=["auto", "fp32r", "fp64"],
-                    help="auto: FP64 on grids up to 1.5e6 nodes (the single atom, fcc2, fcc5), "
-                         "FP32 CG inside FP64 refinement above (fcc10)")
-    ap.add_argument("--no-fp64-ref", action="store_true", help="skip the solve in the other precision")
+                    help="auto: the workload's specified precision (FP32-refined for fcc5 and fcc10, "
+                         "FP64 for the single atom and fcc2)")
+    ap.add_argument("--inner", type=int, default=2, help="hotpath: nonlinear-CG steps per pass")
+    ap.add_argument("--no-other-precision", action="store_true", help="skip the pass in the other precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
-    ap.add_argument("--sample-every", type=int, default=64,
-                    help="CG kernel launches per timed sample (an event-stamped launch costs a few us more)")
-    ap.add_argument("--cg-schedule", type=int, default=-1, choices=[-1, 0, 1, 2],
-                    help="CG launches per iteration: 0/1 two launches, 2 pipelined (one launch, FP64 only), "
-                         "-1 the library's automatic choice")
-    ap.add_argument("--mode", default="solve", choices=["solve", "stencil", "counters", "serve", "relax", "methods", "large"],
-                    help="stencil: only the streaming stencil measurement; counters: a short refined "
-                         "Poisson solve and a reference copy (for counter passes); serve: the request "
-                         "stream of fcc 1-3 clusters through the serving loop")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="length of each oracle sample")
+    ap.add_argument("--sample-every", type=int, default=16,
+                    help="CG iterations per timed sample (an event-stamped launch costs a few us more)")
+    ap.add_argument("--cg-schedule", type=int, default=-1, choices=[-1, 0, 1, 2])
+    ap.add_argument("--mode", default="hotpath",
+                    choices=["hotpath", "ground_state", "stencil", "counters", "serve", "relax", "methods", "large"])
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KEY"),
                     help="write profiles/traffic.json entry KEY from two rocprofv3 counter CSVs of --mode counters")
     ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
-    ap.add_argument("--rate-factor", type=float, default=1.0,
-                    help="serve: arrival rate as a multiple of the sequential FP64 service rate")
+    ap.add_argument("--rate-factors", default="0.5,1,2",
+                    help="serve: arrival rates as multiples of the sequential FP64 service rate")
     ap.add_argument("--slots", type=int, default=4, help="serve: concurrent request slots")
     return ap.parse_args()
 
 
+def specified_precision(lib, S, precision):
+    if precision == "fp32r":
+        return lib.FP32_REFINED
+    if precision == "fp64":
+        return lib.FP64
+    return lib.FP32_REFINED if S.name in ("fcc5", "fcc10") else lib.FP64
+
+
+# ----------------------------------------------------------------- counter summaries
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
-
-
-def traffic_for(kernel_key, path=TRAFFIC_JSON):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source; else None."""
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        data = json.load(f)
-    ent = data.get(kernel_key)
-    if not ent or ent.get("kernels_sha256_16") != kernel_digest():
-        return None
-    return ent.get("bytes_per_launch")
 
 
 def kernel_digest():
@@ -89,70 +98,249 @@ def kernel_digest():
     return h.hexdigest()[:16]
 
 
+def traffic_for(key, path=TRAFFIC_JSON):
+    """Fabric bytes per CG iteration from the committed counter summary, if it was taken on
+    the current kernel source; else None."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        ent = json.load(f).get(key)
+    if not ent or ent.get("kernels_sha256_16") != kernel_digest():
+        return None
+    return ent.get("bytes_per_iteration")
+
+
 def summarize_counters(fetch_csv, write_csv, key, path=TRAFFIC_JSON):
-    """HBM bytes per launch of the CG stencil kernel from a FETCH_SIZE pass and a WRITE_SIZE
+    """Bytes per CG iteration of the FP32 CG kernels (the stencil launch k_stencil2<float, ...,
+    CGP1LOp<float>> and the update k_cg_update<float>) from a FETCH_SIZE pass and a WRITE_SIZE
     pass (KiB per dispatch) of --mode counters, each scaled by what the same counter reads for
-    the reference copy of 256 MiB in that run.  Updates the summary file (profiles/traffic.json)
-    at key."""
+    the reference copy of 256 MiB in that run (FETCH_SIZE counts a 128-byte read request of
+    this part as 64 bytes: its copy reads 128 MiB of the 256).  Updates profiles/traffic.json."""
     import csv
 
     def per_kernel(csv_path, counter):
         out = {}
         with open(csv_path) as f:
             for r in csv.DictReader(f):
-                if r["Counter_Name"] != counter:
-                    continue
-                out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+                if r["Counter_Name"] == counter:
+                    out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
         return out
 
     copy_bytes = 256 * 1024 * 1024
     res = {}
     for csv_path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
         pk = per_kernel(csv_path, counter)
-        name = "CGPipeOp<double>" if key.startswith("cgpipe") else "CGP1LOp<float>"
-        cg = [v for k, vs in pk.items() if name in k and "k_stencil" in k for v in vs]
-        cp = [v for k, vs in pk.items() if "elementwise" in k or "copy" in k.lower() for v in vs]
+        st = [v for k, vs in pk.items() if "CGP1LOp<float>" in k and "k_stencil" in k for v in vs]
+        up = [v for k, vs in pk.items() if "k_cg_update<float" in k for v in vs]
+        cp = [v for k, vs in pk.items() if "copyBuffer" in k or "elementwise" in k for v in vs]
         cp = [v for v in cp if v > 0.5 * max(cp)] if cp else []
-        if not cg or not cp:
-            raise SystemExit(f"{csv_path}: no CG stencil or copy dispatches with {counter}")
-        kib_cg = sum(cg) / len(cg)
-        kib_copy = sum(cp) / len(cp)
-        scale = copy_bytes / (kib_copy * 1024.0)
-        res[counter] = {"kib_per_dispatch": round(kib_cg, 1), "copy_kib": round(kib_copy, 1),
-                        "scale": round(scale, 4), "bytes": round(kib_cg * 1024.0 * scale)}
+        if not st or not up or not cp:
+            raise SystemExit(f"{csv_path}: no CG or copy dispatches with {counter}")
+        scale = copy_bytes / (sum(cp) / len(cp) * 1024.0)
+        kst, kup = sum(st) / len(st), sum(up) / len(up)
+        res[counter] = {"stencil_kib_per_dispatch": round(kst, 1), "update_kib_per_dispatch": round(kup, 1),
+                        "copy_kib": round(sum(cp) / len(cp), 1), "scale": round(scale, 4),
+                        "bytes_per_iteration": round((kst + kup) * 1024.0 * scale)}
     data = json.load(open(path)) if os.path.exists(path) else {}
     data[key] = {"kernels_sha256_16": kernel_digest(),
-                 "bytes_per_launch": res["FETCH_SIZE"]["bytes"] + res["WRITE_SIZE"]["bytes"],
-                 "read_bytes": res["FETCH_SIZE"]["bytes"], "write_bytes": res["WRITE_SIZE"]["bytes"],
-                 "counters": res}
+                 "bytes_per_iteration": res["FETCH_SIZE"]["bytes_per_iteration"] +
+                 res["WRITE_SIZE"]["bytes_per_iteration"],
+                 "read_bytes": res["FETCH_SIZE"]["bytes_per_iteration"],
+                 "write_bytes": res["WRITE_SIZE"]["bytes_per_iteration"], "counters": res}
     with open(path, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)
     print(json.dumps(data[key]))
 
 
-def cpu_baseline(system, seconds):
-    """The oracle's conjugate-gradient Poisson iterations on the same workload's grid and
-    right-hand side (u0^2 + b with the multipole boundary values), as stencil point
-    updates per second; the iteration count is chosen to take about `seconds`."""
-    import numpy as np
+# ----------------------------------------------------------------- CPU baseline
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
+
+def cpu_baseline(system, seconds):
+    """The oracle's conjugate-gradient Poisson iterations on the workload's grid and right-hand
+    side (u0^2 + b with the multipole boundary values), as stencil point updates per second,
+    with all host threads and with one; each sample takes about `seconds`."""
     import oracle
     from paper_1405_6456_amd import synth
 
-    u0 = synth.initial_u(system.grid, system.N)
+    u0 = synth.atomic_guess(system)
     b = oracle.pseudocharge(system)
     rhs = oracle.poisson_rhs(system.grid, 6, 1, u0 * u0 + b)
-    t = time.perf_counter()
-    _, it1, _, _ = oracle.poisson_cg(system.grid, 6, rhs, tol=1e-300, maxit=2)
-    per = (time.perf_counter() - t) / 3.0  # initial residual + 2 iterations
-    iters = max(2, int(seconds / max(per, 1e-6)))
-    t = time.perf_counter()
-    _, it, _, _ = oracle.poisson_cg(system.grid, 6, rhs, tol=1e-300, maxit=iters)
-    dt = time.perf_counter() - t
     pts = system.grid.npts
-    return {"value": (it + 1) * pts / dt / 1e9, "unit": "Gpts/s", "cores": oracle.get_threads(), "kind": "oracle",
-            "sample": f"oracle CG Poisson on the {system.name} grid ({pts} nodes), {it} iterations + initial "
-                      f"residual in {dt:.1f} s (stencil point updates per second of the same operator)"}
+
+    def rate():
+        t = time.perf_counter()
+        oracle.poisson_cg(system.grid, 6, rhs, tol=1e-300, maxit=2)
+        per = (time.perf_counter() - t) / 3.0  # initial residual + 2 iterations
+        iters = max(2, int(seconds / max(per, 1e-6)))
+        t = time.perf_counter()
+        _, it, _, _ = oracle.poisson_cg(system.grid, 6, rhs, tol=1e-300, maxit=iters)
+        dt = time.perf_counter() - t
+        return (it + 1) * pts / dt / 1e9, it, dt
+
+    threads = oracle.get_threads()
+    v_all, it_all, dt_all = rate()
+    oracle.set_threads(1)
+    v_one, it_one, dt_one = rate()
+    oracle.set_threads(threads)
+    return {"value": v_all, "unit": "Gpts/s", "cores": threads, "kind": "oracle", "value_1thread": v_one,
+            "cpu_model": cpu_model(),
+            "sample": f"oracle CG Poisson on the {system.name} grid ({pts} nodes): {it_all} iterations + initial "
+                      f"residual in {dt_all:.1f} s on {threads} threads, {it_one} in {dt_one:.1f} s on one "
+                      f"(stencil point updates per second of the same operator)"}
+
+
+# ----------------------------------------------------------------- helpers
+def stencil_streaming(ctx, n, reps=50):
+    """Plain stencil over six rotating buffer pairs, FP64 and FP32: Gpts/s and the fraction of
+    the HBM peak at 16 / 8 bytes per point."""
+    npts = n[0] * n[1] * n[2]
+    out = {}
+    for dt, name, es in ((0, "f64", 8), (1, "f32", 4)):
+        ms = ctx.bench_stencil(n, 6, dt, reps=reps, nbuf=6)
+        out[name] = {"ms": round(ms, 5), "gpts": round(npts / (ms * 1e-3) / 1e9, 1),
+                     "hbm_frac": round(npts * STENCIL_BYTES[es] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    return out
+
+
+def cg_roofline(ctx, lib, prec, key):
+    """The dominant kernel pair of the pass: one CG iteration of the precision's inner solve."""
+    dt_idx = 1 if prec == lib.FP32_REFINED else 0
+    es = 4 if prec == lib.FP32_REFINED else 8
+    n, ms, pts, sched, first, second = ctx.cg_kernel_stats(dt_idx, split=True)
+    alg = CG_ITER_BYTES[es] * pts
+    achieved = alg / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    names = {0: "k_stencil2<CGP1Op> + k_cg_update", 1: "k_stencil2<CGP1LOp> + k_cg_update",
+             2: "k_stencil2<CGPipeOp>"}
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(key),
+            "kernel": f"CG iteration ({'FP32' if es == 4 else 'FP64'}): {names.get(sched, '?')}",
+            "alg_bytes_per_iteration": alg, "mean_iteration_ms": round(ms, 5),
+            "first_launch_ms": round(first, 5), "second_launch_ms": round(second, 5), "timed_iterations": n,
+            "schedule": sched}
+
+
+# ----------------------------------------------------------------- modes
+def hotpath(args):
+    import numpy as np
+    import torch
+
+    import paper_1405_6456_amd as lib
+    from paper_1405_6456_amd import synth
+
+    S = synth.config(args.workload)
+    npts = S.grid.npts
+    prec = specified_precision(lib, S, args.precision)
+    ctx = lib.Context(0)
+    ctx.set_cg_schedule(args.cg_schedule)
+    guess = lib.default_params(initial_guess=lib.GUESS_ATOMIC)
+    u0 = ctx.initial_guess(S, guess)  # resident in HBM before the timed region
+    step_prm = lambda p: lib.default_params(precision=p, max_outer=1, max_inner=args.inner)
+
+    for _ in range(args.warmup):
+        ctx.solve_device(S, step_prm(prec), u0, want_forces=True)
+    ctx.profile_cg_kernel(args.sample_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [ctx.solve_device(S, step_prm(prec), u0, want_forces=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    key = f"cg_{'f32' if prec == lib.FP32_REFINED else 'f64'}_{S.name}"
+    roofline = cg_roofline(ctx, lib, prec, key)
+    ctx.profile_cg_kernel(0)
+    last = outs[-1]
+    mv = sum(o["matvec_fp64"] + o["matvec_fp32"] for o in outs)
+    line = {
+        "metric": METRIC,
+        "value": round(mv * npts / wall / 1e9, 2),
+        "unit": "Gpts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 stencil/CG + f64 refinement" if prec == lib.FP32_REFINED else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{S.name}: {S.M}-atom Al-like fcc cluster, {S.grid.n[0]}^3 nodes, h={S.grid.h}, "
+                               f"order 12, {'FP32 CG + FP64 refinement' if prec == lib.FP32_REFINED else 'FP64'}"
+                               f"; one hot-path pass per step (setup, {args.inner} nonlinear-CG steps, forces)",
+                   "atoms": S.M, "nodes": npts, "parallelism": "single GPU"},
+        "counts": {k: last[k] for k in ("outer", "inner", "grad_evals", "poisson_solves", "cg_iters", "matvec_fp64",
+                                        "matvec_fp32", "refinements")},
+        "E_total": last["E_total"],
+    }
+    if not args.no_other_precision:
+        other = lib.FP64 if prec == lib.FP32_REFINED else lib.FP32_REFINED
+        ctx.solve_device(S, step_prm(other), u0, want_forces=True)
+        ctx.profile_cg_kernel(args.sample_every)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        reps = 3
+        oth = [ctx.solve_device(S, step_prm(other), u0, want_forces=True) for _ in range(reps)][-1]
+        torch.cuda.synchronize()
+        t_oth = (time.perf_counter() - t) / reps
+        okey = f"cg_{'f32' if other == lib.FP32_REFINED else 'f64'}_{S.name}"
+        oroof = cg_roofline(ctx, lib, other, okey)
+        ctx.profile_cg_kernel(0)
+        t_main = wall / args.steps
+        r32, r64 = (last, oth) if prec == lib.FP32_REFINED else (oth, last)
+        t32, t64 = (t_main, t_oth) if prec == lib.FP32_REFINED else (t_oth, t_main)
+        line["other_precision_pass"] = {"dtype": "f64" if other == lib.FP64 else "f32r", "ms_per_step":
+                                        round(1e3 * t_oth, 2), "cg_iters": oth["cg_iters"], "roofline": oroof}
+        line["speedup_fp32r_vs_fp64"] = round(t64 / t32, 3)
+        line["err_fp32r_vs_fp64"] = {"E_per_atom": abs(r32["E_total"] - r64["E_total"]) / S.M,
+                                     "F_max": float(np.abs(r32["forces"] - r64["forces"]).max())}
+    line["stencil_streaming_185"] = stencil_streaming(ctx, synth.config("fcc10").grid.n)
+    line["roofline"] = roofline
+    line["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(S, args.cpu_seconds)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+def ground_state(args):
+    """Time to converged energy and forces on the workload, FP32-refined and FP64, from the
+    atomic-density guess; the error of the refined result against the FP64 one."""
+    import numpy as np
+    import torch
+
+    import paper_1405_6456_amd as lib
+    from paper_1405_6456_amd import synth
+
+    S = synth.config(args.workload)
+    ctx = lib.Context(0)
+    u0 = ctx.initial_guess(S, lib.default_params(initial_guess=lib.GUESS_ATOMIC))
+    res = {}
+    for name, prec in (("f32r", lib.FP32_REFINED), ("f64", lib.FP64)):
+        ctx.profile_cg_kernel(args.sample_every)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        o = ctx.solve_device(S, lib.default_params(precision=prec), u0, want_forces=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        roof = cg_roofline(ctx, lib, prec, f"cg_{'f32' if prec == lib.FP32_REFINED else 'f64'}_{S.name}")
+        ctx.profile_cg_kernel(0)
+        res[name] = o
+        print(json.dumps({"mode": "ground_state", "workload": S.name, "precision": name, "status": o["status"],
+                          "wall_s": round(wall, 2), "E_total": o["E_total"], "E_per_atom": o["E_total"] / S.M,
+                          "outer": o["outer"], "inner": o["inner"], "cg_iters": o["cg_iters"],
+                          "matvecs": o["matvec_fp64"] + o["matvec_fp32"], "grad_norm": o["grad_norm"],
+                          "gpts": round((o["matvec_fp64"] + o["matvec_fp32"]) * S.grid.npts / wall / 1e9, 1),
+                          "roofline": roof}), flush=True)
+    print(json.dumps({"mode": "ground_state", "workload": S.name,
+                      "err_fp32r_vs_fp64": {"E_per_atom": abs(res["f32r"]["E_total"] - res["f64"]["E_total"]) / S.M,
+                                            "F_max": float(np.abs(res["f32r"]["forces"] - res["f64"]["forces"]).max())}}),
+          flush=True)
+    ctx.close()
 
 
 def fifo_latencies(arrivals, service):
@@ -174,9 +362,10 @@ def pct(v, q):
 
 def serve(args):
     """Request stream: fcc m^3 clusters, m ~ U{1,2,3} (seed 2014), displacement seed 10000+k,
-    Poisson arrivals (seed 2015) at rate_factor x the sequential FP64 service rate; served
-    with FP32+FP64-refined solves through the serving loop, against a FIFO replay of the
-    same arrivals with the measured sequential FP64 service times."""
+    Poisson arrivals (seed 2015) at f x the sequential FP64 service rate for each f of
+    --rate-factors; served with FP32-refined solves (the stream's specified precision) through
+    the serving loop, against a FIFO replay of the same arrivals with the measured sequential
+    FP64 service times.  One JSON line per f."""
     import threading
 
     import numpy as np
@@ -185,90 +374,78 @@ def serve(args):
     from paper_1405_6456_amd import synth
 
     reqs = synth.serving_requests(args.requests)
-    ms = [S.M // 4 for S in reqs]
-    ms = [round(m ** (1 / 3)) for m in ms]
+    ms = [round((S.M // 4) ** (1 / 3)) for S in reqs]
     ctx = lib.Context(0)
-    # sequential FP64 service time per cluster size (first request of each size), after a warm-up
-    ctx.solve(reqs[0], lib.default_params(), None, want_fields=False)
-    svc64, first = {}, {}
+    prm64 = lib.default_params(initial_guess=lib.GUESS_ATOMIC)
+    prm32 = lib.default_params(precision=lib.FP32_REFINED, initial_guess=lib.GUESS_ATOMIC)
+    ctx.solve(reqs[0], prm64, None, want_fields=False)  # warm-up
+    first = {}
     for k, m in enumerate(ms):
-        if m not in first:
-            first[m] = k
+        first.setdefault(m, k)
+    svc64, ref = {}, {}
     for m, k in sorted(first.items()):
         t = time.perf_counter()
-        ctx.solve(reqs[k], lib.default_params(), None, want_fields=False)
+        ref[m] = ctx.solve(reqs[k], prm64, None, want_fields=False)
         svc64[m] = time.perf_counter() - t
     service = [svc64[m] for m in ms]
     c_seq = 1.0 / (sum(service) / len(service))
-    rate = args.rate_factor * c_seq
-    arrivals = synth.arrival_times(len(reqs), rate)
-    seq_lat = fifo_latencies(list(arrivals), service)
+    for f in [float(x) for x in args.rate_factors.split(",")]:
+        rate = f * c_seq
+        arrivals = synth.arrival_times(len(reqs), rate)
+        seq_lat = fifo_latencies(list(arrivals), service)
+        srv = lib.Server(0, max_slots=args.slots)
+        tickets = [None] * len(reqs)
+        t0 = time.perf_counter()
 
-    srv = lib.Server(0, max_slots=args.slots)
-    prm = lib.default_params(precision=lib.FP32_REFINED)
-    tickets = [None] * len(reqs)
-    t0 = time.perf_counter()
+        def submitter():
+            for k, S in enumerate(reqs):
+                d = arrivals[k] - (time.perf_counter() - t0)
+                if d > 0:
+                    time.sleep(d)
+                tickets[k] = srv.submit(S, prm32)
 
-    def submitter():
-        for k, S in enumerate(reqs):
-            d = arrivals[k] - (time.perf_counter() - t0)
-            if d > 0:
-                time.sleep(d)
-            tickets[k] = srv.submit(S, prm)
-
-    th = threading.Thread(target=submitter)
-    th.start()
-    results = [None] * len(reqs)
-    pending = set(range(len(reqs)))
-    while pending:
-        for k in list(pending):
-            if tickets[k] is not None:
-                r = srv.poll(tickets[k])
-                if r is not None:
-                    results[k] = r
-                    pending.discard(k)
-                    print(f"request {k} done ({len(reqs) - len(pending)}/{len(reqs)})", file=sys.stderr, flush=True)
-        time.sleep(0.005)
-    th.join()
-    wall = time.perf_counter() - t0
-    st = srv.stats()
-    srv.close()
-    # accuracy of served results against the FP64 path, one request per size
-    err_e, err_f = 0.0, 0.0
-    for m, k in sorted(first.items()):
-        ref = ctx.solve(reqs[k], lib.default_params(), None, want_fields=False)
-        err_e = max(err_e, abs(results[k]["E_total"] - ref["E_total"]) / reqs[k].M)
-        err_f = max(err_f, float(np.abs(results[k]["forces"] - ref["forces"]).max()))
+        th = threading.Thread(target=submitter)
+        th.start()
+        results = [None] * len(reqs)
+        pending = set(range(len(reqs)))
+        while pending:
+            for k in list(pending):
+                if tickets[k] is not None:
+                    r = srv.poll(tickets[k])
+                    if r is not None:
+                        results[k] = r
+                        pending.discard(k)
+            time.sleep(0.005)
+        th.join()
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        print(f"serve f={f}: {st['completed']} done in {wall:.1f} s", file=sys.stderr, flush=True)
+        err_e = max(abs(results[k]["E_total"] - ref[m]["E_total"]) / reqs[k].M for m, k in first.items())
+        err_f = max(float(np.abs(results[k]["forces"] - ref[m]["forces"]).max()) for m, k in first.items())
+        print(json.dumps({
+            "metric": METRIC, "mode": "serve", "value": round(st["solves_per_s"], 4), "unit": "solves/s",
+            "n_gpus": 1, "higher_is_better": True, "dtype": "f32 stencil/CG + f64 refinement", "data": "synthetic",
+            "config": {"workload": f"serving stream: {len(reqs)} fcc m^3 clusters, m in {{1,2,3}} (48^3..79^3 nodes),"
+                                   f" Poisson arrivals at {f} x the sequential FP64 rate", "slots": args.slots},
+            "served": {"p50_ms": round(st["p50_ms"], 1), "p99_ms": round(st["p99_ms"], 1),
+                       "mean_ms": round(st["mean_ms"], 1), "solves_per_s": round(st["solves_per_s"], 4),
+                       "wall_s": round(wall, 1), "completed": st["completed"],
+                       "statuses": sorted(set(r["status"] for r in results))},
+            "sequential_fp64": {"p50_ms": round(1e3 * pct(seq_lat, 0.5), 1), "p99_ms": round(1e3 * pct(seq_lat, 0.99), 1),
+                                "service_s": {str(m): round(v, 3) for m, v in svc64.items()},
+                                "capacity_solves_per_s": round(c_seq, 4)},
+            "arrival_rate_per_s": round(rate, 4),
+            "err_vs_fp64": {"E_per_atom": err_e, "F_max": err_f}}), flush=True)
     ctx.close()
-    line = {
-        "metric": "Gpts/s stencil (%HBM peak); AL-OFDFT solves/s, p50/p99 latency vs FP64",
-        "value": round(st["solves_per_s"], 4),
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "higher_is_better": True,
-        "dtype": "f32 stencil/CG + f64 refinement",
-        "data": "synthetic",
-        "config": {"workload": f"serving stream: {len(reqs)} fcc m^3 clusters, m in {{1,2,3}} "
-                               f"(48^3..79^3 nodes), Poisson arrivals at {args.rate_factor} x sequential "
-                               f"FP64 rate", "slots": args.slots},
-        "served": {"p50_ms": round(st["p50_ms"], 1), "p99_ms": round(st["p99_ms"], 1),
-                   "mean_ms": round(st["mean_ms"], 1), "solves_per_s": round(st["solves_per_s"], 4),
-                   "wall_s": round(wall, 1), "completed": st["completed"],
-                   "statuses": sorted(set(r["status"] for r in results))},
-        "sequential_fp64": {"p50_ms": round(1e3 * pct(seq_lat, 0.5), 1), "p99_ms": round(1e3 * pct(seq_lat, 0.99), 1),
-                            "service_s": {str(m): round(v, 3) for m, v in svc64.items()},
-                            "solves_per_s": round(c_seq, 4)},
-        "arrival_rate_per_s": round(rate, 4),
-        "err_vs_fp64": {"E_per_atom": err_e, "F_max": err_f},
-    }
-    print(json.dumps(line), flush=True)
 
 
 def methods_mode():
     """The paper's method comparison on the synthetic workloads (Sec. 5.3): the augmented
-    Lagrangian against the penalty method (eta fixed at 0) on the single atom and the 32-atom
-    cluster, and the augmented Lagrangian's sensitivity to eta0, mu0 and kappa on the single
-    atom -- stencil applications (the paper's cost measure), iterations, energy, time.  FP64."""
+    Lagrangian, the penalty method (eta fixed at 0) and the Lagrange-multiplier method on the
+    single atom and the 32-atom cluster, and the augmented Lagrangian's sensitivity to eta0,
+    mu0 and kappa on the 32-atom cluster -- stencil applications (the paper's cost measure),
+    iterations, energy, time.  FP64."""
     import torch
 
     import paper_1405_6456_amd as lib
@@ -278,36 +455,36 @@ def methods_mode():
 
     def run(name, quiet=False, **kw):
         S = synth.config(name)
-        u0 = synth.initial_u(S.grid, S.N) if name == "single" else synth.atomic_guess(S)
-        u0d = torch.from_numpy(u0).to("cuda:0").contiguous()
         prm = lib.default_params(precision=lib.FP64, **kw)
+        u0 = ctx.initial_guess(S, lib.default_params(initial_guess=lib.GUESS_ATOMIC if name != "single" else
+                                                     lib.GUESS_UNIFORM))
         torch.cuda.synchronize()
         t = time.perf_counter()
-        o = ctx.solve_device(S, prm, u0d, want_forces=False)
+        o = ctx.solve_device(S, prm, u0, want_forces=False)
         wall = time.perf_counter() - t
-        line = {"mode": "methods", "workload": name, **kw, "status": o["status"], "matvecs": o["matvec_fp64"],
-                "outer": o["outer"], "inner": o["inner"], "E_per_atom": o["E_total"] / S.M, "eta_star": o["eta_star"],
-                "C_h_per_N": o["C_h"] / S.N, "wall_s": round(wall, 3)}
         if not quiet:
-            print(json.dumps(line), flush=True)
+            print(json.dumps({"mode": "methods", "workload": name, **kw, "status": o["status"],
+                              "matvecs": o["matvec_fp64"], "outer": o["outer"], "inner": o["inner"],
+                              "E_per_atom": o["E_total"] / S.M, "eta_star": o["eta_star"],
+                              "grad_norm": o["grad_norm"], "C_h_per_N": o["C_h"] / S.N,
+                              "wall_s": round(wall, 3)}), flush=True)
         return o
 
     run("single", quiet=True)  # warm-up
     for name in ("single", "fcc2"):
-        for method in (lib.AL, lib.PENALTY):
+        for method in (lib.AL, lib.PENALTY, lib.LAGRANGE):
             run(name, method=method)
     for eta0, mu0, kappa in ((0.0, 1.0, 0.1), (-0.4, 1.0, 0.1), (-0.2, 0.1, 0.1), (-0.2, 10.0, 0.1),
                              (-0.2, 1.0, 0.01), (-0.2, 1.0, 0.5)):
-        run("single", eta0=eta0, mu0=mu0, kappa=kappa)
+        run("fcc2", eta0=eta0, mu0=mu0, kappa=kappa)
     ctx.close()
 
 
 def large_mode():
     """The size of the paper's largest cluster on one device: 29^3 fcc cells (97 556 atoms),
-    474^3 = 106.5 M nodes.  A full ground state there takes hours, so this times its hot step:
-    the pseudocharge of all atoms, and Poisson solves (multipole boundary values, tolerance
-    1e-10, from a zero guess) of the charge u0^2 + b with the atomic-density guess, in FP64 and
-    FP32-refined, with the CG kernel's roofline fraction; and the plain stencil at that size."""
+    474^3 = 106.5 M nodes: the pseudocharge of all atoms, Poisson solves (multipole boundary
+    values, 1e-10, from zero) of u0^2 + b with the atomic-density guess in FP64 and
+    FP32-refined with their CG-iteration roofline, and the plain stencil at that size."""
     import torch
 
     import paper_1405_6456_amd as lib
@@ -320,40 +497,32 @@ def large_mode():
     t = time.perf_counter()
     b, _ = ctx.pseudocharge(S)
     torch.cuda.synchronize()
-    t_b = time.perf_counter() - t
-    print(json.dumps({"mode": "large", "step": "pseudocharge", "atoms": S.M, "nodes": g.npts, "ms": round(1e3 * t_b, 1),
+    print(json.dumps({"mode": "large", "step": "pseudocharge", "atoms": S.M, "nodes": g.npts,
+                      "ms": round(1e3 * (time.perf_counter() - t), 1),
                       "neutrality": float(g.h ** 3 * b.sum().item() + S.Z.sum())}), flush=True)
-    u0 = torch.from_numpy(synth.atomic_guess(S)).to("cuda:0")
+    u0 = ctx.initial_guess(S, lib.default_params(initial_guess=lib.GUESS_ATOMIC))
     rho = (u0 * u0 + b).contiguous()
     del u0
-    for prec, name, es, per_node in ((lib.FP64, "f64", 8, 5), (lib.FP32_REFINED, "f32r", 4, 5)):
+    for prec, name in ((lib.FP64, "f64"), (lib.FP32_REFINED, "f32r")):
         ctx.profile_cg_kernel(64)
         torch.cuda.synchronize()
         t = time.perf_counter()
         phi, its, rel = ctx.poisson(rho, g, bc=lib.BC_MULTIPOLE, precision=prec, tol=1e-10)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t
-        n_t, ms, pts, sched = ctx.cg_kernel_stats(0 if prec == lib.FP64 else 1)
+        roof = cg_roofline(ctx, lib, prec, f"cg_{'f32' if prec == lib.FP32_REFINED else 'f64'}_fcc29")
         ctx.profile_cg_kernel(0)
-        alg = (12 if sched == 2 else 5) * es * g.npts
         print(json.dumps({"mode": "large", "step": f"poisson_{name}", "cg_iters": its, "relres": rel,
                           "wall_s": round(wall, 3), "us_per_iter": round(1e6 * wall / max(1, its), 1),
-                          "gpts": round(its * g.npts / wall / 1e9, 1), "cg_kernel_schedule": sched,
-                          "cg_kernel_ms": round(ms, 4),
-                          "cg_kernel_hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ms > 0 else None}),
-              flush=True)
+                          "roofline": roof}), flush=True)
         del phi
-    for dt, name, es in ((0, "f64", 8), (1, "f32", 4)):
-        ms = ctx.bench_stencil(g.n, 6, dt, reps=10, nbuf=2)
-        print(json.dumps({"mode": "large", "step": f"stencil_{name}", "gpts": round(g.npts / (ms * 1e-3) / 1e9, 1),
-                          "hbm_frac": round(g.npts * 2 * es / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}), flush=True)
+    print(json.dumps({"mode": "large", "step": "stencil", **stencil_streaming(ctx, g.n, reps=10)}), flush=True)
     ctx.close()
 
 
 def relax_mode():
     """Relaxation of the two-atom analogue of the paper's Al2 case (Z = 3, Gaussian
-    pseudocharges, 27^3 nodes at h = 0.9 Bohr) from 4.0 Bohr apart to ftol = 2e-4 Ha/Bohr:
-    wall time, nonlinear CG steps, ground-state solves and the bond length reached."""
+    pseudocharges, 27^3 nodes at h = 0.9 Bohr) from 4.0 Bohr apart to ftol = 2e-4 Ha/Bohr."""
     import numpy as np
     import torch
 
@@ -381,33 +550,49 @@ def relax_mode():
     ctx.close()
 
 
-def counters_mode(S, schedule, precision):
-    """A short Poisson solve on the workload grid in the bench's precision for it (its CG
-    kernel is the one of interest), then a 256 MiB reference copy whose counter readings
-    scale the byte counters."""
+def reference_copy():
+    """A 256 MiB device-to-device copy, whose counter readings calibrate the byte counters."""
+    import torch
+
+    src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"reference_copy_bytes_read": src.numel() * 8, "bytes_written": dst.numel() * 8}), flush=True)
+
+
+def counters_mode(args):
+    """A short Poisson solve on the workload grid in its specified precision (its CG kernels
+    are the ones of interest), then the reference copy."""
     import torch
 
     import paper_1405_6456_amd as lib
     from paper_1405_6456_amd import synth
 
+    S = synth.config(args.workload)
     ctx = lib.Context(0)
-    ctx.set_cg_schedule(schedule)
-    u0 = synth.initial_u(S.grid, S.N)
+    ctx.set_cg_schedule(args.cg_schedule)
+    u0 = ctx.initial_guess(S, lib.default_params(initial_guess=lib.GUESS_ATOMIC))
     b, _ = ctx.pseudocharge(S)
-    rho = (torch.from_numpy(u0 * u0).to("cuda:0") + b).contiguous()
-    if precision == "auto":
-        prec = lib.FP32_REFINED if S.grid.npts > 1_500_000 else lib.FP64
-    else:
-        prec = lib.FP32_REFINED if precision == "fp32r" else lib.FP64
-    _, its, rel = ctx.poisson(rho, S.grid, precision=prec, tol=1e-10, max_cg=200)
+    rho = (u0 * u0 + b).contiguous()
+    _, its, rel = ctx.poisson(rho, S.grid, precision=specified_precision(lib, S, args.precision), tol=1e-10,
+                              max_cg=200)
     torch.cuda.synchronize()
-    src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    print(json.dumps({"workload": S.name, "cg_iters": its, "relres": rel, "reference_copy_bytes": 2 * src.numel() * 8}),
-          flush=True)
+    print(json.dumps({"workload": S.name, "cg_iters": its, "relres": rel}), flush=True)
     ctx.close()
+    reference_copy()
+
+
+def stencil_mode(args):
+    import paper_1405_6456_amd as lib
+    from paper_1405_6456_amd import synth
+
+    S = synth.config(args.workload)
+    ctx = lib.Context(0)
+    print(json.dumps({"mode": "stencil", "workload": S.name, "nodes": S.grid.npts,
+                      **stencil_streaming(ctx, S.grid.n, reps=20)}), flush=True)
+    ctx.close()
+    reference_copy()
 
 
 def main():
@@ -418,170 +603,13 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               f"(the solve is not sharded across GPUs)", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
-    import paper_1405_6456_amd as lib
-    from paper_1405_6456_amd import synth
-
     torch.cuda.set_device(0)
-    if args.mode == "serve":
-        return serve(args)
-    if args.mode == "relax":
-        return relax_mode()
-    if args.mode == "methods":
-        return methods_mode()
-    if args.mode == "large":
-        return large_mode()
-    S = synth.config(args.workload)
-    if args.mode == "counters":
-        return counters_mode(S, args.cg_schedule, args.precision)
-    if args.mode == "stencil":
-        ctx = lib.Context(0)
-        for dt in (0, 1):
-            ms = ctx.bench_stencil(S.grid.n, 6, dt, reps=20, nbuf=6)
-            es = 8 if dt == 0 else 4
-            print(json.dumps({"stencil": "f64" if dt == 0 else "f32", "nodes": S.grid.npts, "ms": ms,
-                              "gpts": S.grid.npts / (ms * 1e-3) / 1e9,
-                              "hbm_frac": S.grid.npts * 2 * es / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}), flush=True)
-        # reference copy of a known size (2 x 256 MiB moved), to scale the HBM byte counters
-        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"reference_copy_bytes_read": src.numel() * 8, "bytes_written": dst.numel() * 8}),
-              flush=True)
-        ctx.close()
-        return
-    # clusters start from a superposition of atomic densities (the paper's practice; the
-    # uniform guess stalls the 4000-atom cluster far from the minimiser); the single atom
-    # from the seeded uniform guess of its configuration
-    u0 = synth.initial_u(S.grid, S.N) if args.workload == "single" else synth.atomic_guess(S)
-    if args.precision == "auto":
-        # FP32 pays only where the CG iterations are bandwidth bound; below, the FP64 path
-        # (pipelined CG) is faster, and it is what the smaller workloads are specified in
-        prec = lib.FP32_REFINED if S.grid.npts > 1_500_000 else lib.FP64
-    else:
-        prec = lib.FP32_REFINED if args.precision == "fp32r" else lib.FP64
-    prm = lib.default_params(precision=prec)
-    ctx = lib.Context(0)
-    ctx.set_cg_schedule(args.cg_schedule)
-    npts = S.grid.npts
-    # the initial guess is resident in HBM before the timed region (only the atom list and
-    # the 3M forces cross PCIe inside a solve)
-    u0_dev = torch.from_numpy(u0).to("cuda:0").contiguous()
-
-    for _ in range(args.warmup):
-        ctx.solve_device(S, prm, u0_dev, want_forces=True)
-
-    ctx.profile_cg_kernel(args.sample_every)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    outs = [ctx.solve_device(S, prm, u0_dev, want_forces=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    dt_idx = 1 if prec == lib.FP32_REFINED else 0
-    launches, mean_ms, kpts, sched = ctx.cg_kernel_stats(dt_idx)
-    ctx.profile_cg_kernel(0)
-
-    last = outs[-1]
-    mv = sum(o["matvec_fp64"] + o["matvec_fp32"] for o in outs)
-    ms_per_step = 1e3 * wall / args.steps
-    value = mv * npts / wall / 1e9
-    esize = 4 if prec == lib.FP32_REFINED else 8
-    tag = 'f32' if esize == 4 else 'f64'
-    if sched == 2:
-        # algorithmic bytes of the pipelined CG iteration per node: read w (stencil input),
-        # z, s, p, x, r; write z, s, p, x, r and the next w
-        alg_bytes = 12 * esize * kpts
-        kernel_key = f"cgpipe_stencil_{tag}_{args.workload}"
-        kernel = ("CG iteration, pipelined (m = A w; z = m + beta z, s = w + beta s, p = r + beta p, "
-                  "x += alpha p, r -= alpha s, w -= alpha z; r.r, w.r): k_stencil2 CGPipeOp")
-    elif sched == 0:
-        # read r and p (stencil input p = r + beta p), write p and A p
-        alg_bytes = 4 * esize * kpts
-        kernel_key = f"cgp_stencil_{tag}_{args.workload}"
-        kernel = "CG first half (p = r + beta p, A p, p.Ap): k_stencil2 CGP1Op"
-    else:
-        # algorithmic bytes of the CG stencil kernel per node: read r (stencil input), p and
-        # A p; write p and A p (the first half of each iteration, by linearity)
-        alg_bytes = 5 * esize * kpts
-        kernel_key = f"cg_stencil_{tag}_{args.workload}"
-        kernel = "CG first half (A r; p = r + beta p, A p = A r + beta A p; p.Ap): k_stencil2 CGP1LOp"
-    achieved = alg_bytes / (mean_ms * 1e-3) / 1e9 if mean_ms > 0 else 0.0
-    tr = traffic_for(kernel_key)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr, "kernel": kernel,
-                "alg_bytes_per_launch": alg_bytes, "mean_launch_ms": round(mean_ms, 5), "timed_launches": launches}
-
-    # streaming stencil throughput (six rotating buffer pairs, more than the 256 MB cache)
-    st_ms = ctx.bench_stencil(S.grid.n, 6, 1 if esize == 4 else 0, reps=100, nbuf=6)
-    stencil = {"nodes": npts, "gpts": round(npts / (st_ms * 1e-3) / 1e9, 1),
-               "hbm_frac": round(npts * 2 * esize / (st_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-               "dtype": "f32" if esize == 4 else "f64"}
-    # and on the 4000-atom cluster's grid (185^3), both precisions (x read once, y written once)
-    big = synth.config("fcc10").grid.n
-    nbig = big[0] * big[1] * big[2]
-    stencil_185 = {}
-    for dt, name, es in ((0, "f64", 8), (1, "f32", 4)):
-        ms_b = ctx.bench_stencil(big, 6, dt, reps=50, nbuf=6)
-        stencil_185[name] = {"gpts": round(nbig / (ms_b * 1e-3) / 1e9, 1),
-                             "hbm_frac": round(nbig * 2 * es / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-
-    extra = {}
-    if not args.no_fp64_ref:
-        # the same solve in the other precision: the FP32-refined path's speedup over the
-        # FP64 GPU path and its error against it, whichever of the two is timed above
-        other = lib.FP64 if prec == lib.FP32_REFINED else lib.FP32_REFINED
-        t = time.perf_counter()
-        oth = ctx.solve_device(S, lib.default_params(precision=other), u0_dev, want_forces=True)
-        t_oth = time.perf_counter() - t
-        t_main = wall / args.steps
-        entry = {"ms_per_solve": round(1e3 * t_oth, 1), "status": oth["status"], "cg_iters": oth["cg_iters"],
-                 "E_total": oth["E_total"]}
-        if prec == lib.FP32_REFINED:
-            extra["fp64_path"] = entry
-            t32, t64, r32, r64 = t_main, t_oth, last, oth
-        else:
-            extra["fp32r_path"] = entry
-            t32, t64, r32, r64 = t_oth, t_main, oth, last
-        extra["speedup_fp32r_vs_fp64"] = round(t64 / t32, 3)
-        extra["err_fp32r_vs_fp64"] = {"E_per_atom": abs(r32["E_total"] - r64["E_total"]) / S.M,
-                                      "F_max": float(np.abs(r32["forces"] - r64["forces"]).max())}
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(S, args.cpu_seconds)
-
-    line = {
-        "metric": "Gpts/s stencil (%HBM peak); AL-OFDFT solves/s, p50/p99 latency vs FP64",
-        "value": round(value, 2),
-        "unit": "Gpts/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 1),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32 stencil/CG + f64 refinement" if prec == lib.FP32_REFINED else "f64",
-        "data": "synthetic",
-        "config": {"workload": f"{S.name}: {S.M} atoms, {S.grid.n[0]}^3 nodes, h={S.grid.h}, order 12, "
-                               f"{'FP32+FP64-refined' if prec == lib.FP32_REFINED else 'FP64'} Poisson",
-                   "atoms": S.M, "nodes": npts, "parallelism": "single GPU"},
-        "solves_per_s": round(args.steps / wall, 4),
-        "status": last["status"],
-        "E_total": last["E_total"],
-        "counts": {k: last[k] for k in ("outer", "inner", "grad_evals", "poisson_solves", "cg_iters", "matvec_fp64",
-                                        "matvec_fp32", "refinements")},
-        "stencil_streaming": stencil,
-        "stencil_streaming_185": stencil_185,
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-    }
-    line.update(extra)
-    print(json.dumps(line), flush=True)
-    ctx.close()
+    modes = {"hotpath": lambda: hotpath(args), "ground_state": lambda: ground_state(args),
+             "stencil": lambda: stencil_mode(args), "counters": lambda: counters_mode(args),
+             "serve": lambda: serve(args), "relax": relax_mode, "methods": methods_mode, "large": large_mode}
+    modes[args.mode]()
 
 
 if __name__ == "__main__":

@@ -47,10 +47,29 @@ extern "C" {
 #define ALOFDFT_DEVICE_ERROR (-3)
 #define ALOFDFT_NUMERICAL (-4)
 #define ALOFDFT_REJECTED (-5)
+#define ALOFDFT_CANCELLED (-6)
 
 /* constraint methods (Sec. 3; Sec. 5.3.2 for the two comparison methods) */
 #define ALOFDFT_METHOD_AUGMENTED_LAGRANGIAN 0
 #define ALOFDFT_METHOD_PENALTY 1
+#define ALOFDFT_METHOD_LAGRANGE 2
+
+/* pseudocharge of a nucleus: the Gaussian -Z pi^-3/2 s^-3 exp(-r^2/s^2), or the
+ * construction of Sec. 4, b_J = -(1/4 pi) Delta_h V_J on the nodes (order-2n stencil
+ * applied to V_J = -Z erf(r/s)/r); both on the ball r <= r_cut */
+#define ALOFDFT_PSEUDO_GAUSSIAN 0
+#define ALOFDFT_PSEUDO_FD_LAPLACIAN 1
+
+/* initial guess used when no u0 is passed: sqrt(N/V)(1 + 0.05 xi) (uniform with
+ * seeded noise), or the superposition of atomic densities of Sec. 4 */
+#define ALOFDFT_GUESS_UNIFORM 0
+#define ALOFDFT_GUESS_ATOMIC 1
+
+/* stopping rule of the outer loop: |C_h|/N < tol_constraint, or Algorithm AugLag's
+ * energy change |E_q - E_(q-1)| / M < tol_energy (Sec. 3); both require the inner
+ * problem solved to tol_grad */
+#define ALOFDFT_STOP_CONSTRAINT 0
+#define ALOFDFT_STOP_ENERGY_CHANGE 1
 
 /* boundary values of phi: zero Dirichlet (Sec. 4) or the multipole expansion
  * (monopole + dipole + traceless quadrupole of u^2 + b about the box centre)
@@ -74,7 +93,11 @@ typedef struct {
   int xc;                 /* ALOFDFT_XC_* (default LDA_PZ, Sec. 2) */
   double gauss_width;     /* s of b_J = -Z pi^-3/2 s^-3 exp(-r^2/s^2) (default 1.0) */
   double r_cut;           /* support radius of b_J (default 7.0) */
-  int method;             /* ALOFDFT_METHOD_* (default augmented Lagrangian) */
+  int method;             /* ALOFDFT_METHOD_* (default augmented Lagrangian); LAGRANGE keeps
+                             h^3 sum u^2 = N exactly, eta the Rayleigh quotient, Polak-Ribiere
+                             directions projected orthogonal to u and a Brent search of the
+                             energy along u cos(t) + sqrt(N) d sin(t) (Sec. 5.3.2; eta0, mu0,
+                             kappa, tol_constraint and al_stop unused) */
   double eta0, mu0, kappa; /* Algorithm AugLag inputs (defaults -0.2, 1.0, 0.1, Sec. 5.3.1) */
   double tol_constraint;  /* stop the outer loop at |C_h|/N below this (1e-8) */
   double tol_grad;        /* inner stop: (h^3 sum g^2)^1/2 below this (1e-6) */
@@ -91,6 +114,12 @@ typedef struct {
   int cg_check_every;     /* most CG iterations between host convergence checks (32); the
                              checks are timed by the observed residual reduction */
   uint64_t seed;          /* seed of the default initial guess (6456) */
+  int pseudocharge;       /* ALOFDFT_PSEUDO_* (default Gaussian) */
+  int initial_guess;      /* ALOFDFT_GUESS_* (default uniform) */
+  double guess_width;     /* atomic guess: Gaussian width w of each atom's Z electrons, cut at 5w (1.5) */
+  double guess_floor;     /* atomic guess: uniform floor as a fraction of N/V (1e-3) */
+  int al_stop;            /* ALOFDFT_STOP_* (default constraint) */
+  double tol_energy;      /* energy-change rule, Ha per atom (3.6749e-6 = 1e-4 eV, Sec. 5.3.1) */
 } alofdft_params;
 
 typedef struct {
@@ -138,11 +167,22 @@ const char* alofdft_last_error(const alofdft_ctx* ctx);
 /* Fills *p with the defaults listed above.  Returns ALOFDFT_OK or INVALID_ARGUMENT. */
 int alofdft_default_params(alofdft_params* p);
 
+/* Asks the call running on ctx (a solve, relaxation, Poisson solve or energy
+ * evaluation) to stop: it returns ALOFDFT_CANCELLED at its next check (every host read
+ * of a conjugate-gradient state, at most cg_check_every iterations apart, and every
+ * nonlinear CG step), with its outputs not written.  If no call is running, the next
+ * one on ctx stops at its first check.  The only call on a context that may be made
+ * from another thread while it is in use.  INVALID_ARGUMENT for NULL. */
+int alofdft_cancel(alofdft_ctx* ctx);
+
 /* Creates a context on HIP device `hip_device` that enqueues all work on
  * `hip_stream` (a hipStream_t, borrowed, may be NULL for the null stream).  The
  * context allocates its device workspace lazily and owns it until destroy.  With
  * the environment variable ALOFDFT_PROGRESS set at creation, its solves write one
- * line to stderr per 100 nonlinear-CG steps and per augmented-Lagrangian step. */
+ * line to stderr per 100 nonlinear-CG steps and per augmented-Lagrangian step; with
+ * ALOFDFT_TRACE=path, one line per Poisson solve is appended to that file (counts,
+ * verdicts and exact hashes of the right-hand side and of phi before and after, which
+ * copies three grid arrays to the host per solve: a diagnostic, slow). */
 int alofdft_create(alofdft_ctx** out, int hip_device, void* hip_stream);
 void alofdft_destroy(alofdft_ctx* ctx);
 
@@ -234,9 +274,16 @@ int alofdft_energy_gradient(alofdft_ctx* ctx, const alofdft_system* sys, const a
                             const double* u_dev, double eta, double mu, double* phi_dev, double* g_dev,
                             alofdft_energy* e);
 
-/* Nuclear pseudocharge b = sum_J b_J on the grid (Sec. 4 construction, Gaussian
- * b_J with support r_cut).  b_dev: device grid array.  *self_energy (nullable)
- * receives 1/2 sum_J h^3 sum b_J V_J. */
+/* The initial guess a solve takes when no u0 is passed (prm->initial_guess): the
+ * uniform guess sqrt(N/V)(1 + 0.05 xi) with xi from SplitMix64(seed XOR node), or the
+ * superposition of atomic densities of Sec. 4 (each atom a Gaussian of Z_J electrons of
+ * width guess_width cut at 5 widths, plus guess_floor N/V, scaled to h^3 sum u^2 = N).
+ * u0_dev: device grid array (written).  Errors as alofdft_solve's validation. */
+int alofdft_initial_guess(alofdft_ctx* ctx, const alofdft_system* sys, const alofdft_params* prm, double* u0_dev);
+
+/* Nuclear pseudocharge b = sum_J b_J on the grid (Sec. 4 construction; Gaussian b_J or
+ * the discrete Laplacian of V_J, prm->pseudocharge, support r_cut).  b_dev: device grid
+ * array.  *self_energy (nullable) receives 1/2 sum_J h^3 sum b_J V_J. */
 int alofdft_pseudocharge(alofdft_ctx* ctx, const alofdft_system* sys, const alofdft_params* prm, double* b_dev,
                          double* self_energy);
 
@@ -306,24 +353,27 @@ int alofdft_set_tuning(alofdft_ctx* ctx, int stencil_variant, int target_blocks,
  * INVALID_ARGUMENT for a null context or another value. */
 int alofdft_set_cg_schedule(alofdft_ctx* ctx, int schedule);
 
-/* Measurement of the dominant kernel.  With sample_every > 0, every
- * sample_every-th launch of the conjugate-gradient stencil kernel (the fused
- * first launch of each CG iteration: A r, p, A p and p.Ap with schedule 1;
- * p = r + beta p, A p and p.Ap with schedule 0; the whole iteration with
- * schedule 2) carries a pair of HIP
- * events that the runtime stamps with the start and end of the kernel itself
- * (hipExtLaunchKernel), so the mean is the kernel duration a kernel trace reports;
- * launches made after a solve has converged (which exit at once) are not counted.  sample_every = 0 stops sampling.  Calling it
- * resets the statistics.  INVALID_ARGUMENT for a null context or a negative value. */
+/* Measurement of the dominant kernels.  With sample_every > 0, every
+ * sample_every-th conjugate-gradient iteration has each of its launches (schedules
+ * 0 and 1: the stencil launch -- A r, p, A p and p.Ap with schedule 1; p = r + beta p,
+ * A p and p.Ap with schedule 0 -- and the update x += alpha p, r -= alpha A p, r.r;
+ * schedule 2: the single pipelined launch) carry a pair of HIP events that the
+ * runtime stamps with the start and end of the kernel itself (hipExtLaunchKernel),
+ * so the means are the kernel durations a kernel trace reports; iterations launched
+ * after a solve has converged (which exit at once) are not counted.  sample_every = 0
+ * stops sampling.  Calling it resets the statistics.  INVALID_ARGUMENT for a null
+ * context or a negative value. */
 int alofdft_profile_cg_kernel(alofdft_ctx* ctx, int sample_every);
 
-/* Statistics of the sampled launches for dtype 0 (FP64 CG) or 1 (FP32 inner CG of
- * the refined solve): number of timed launches, mean duration in ms, the grid
- * points (n[0]*n[1]*n[2]) of the last timed launch and, if schedule is not null,
- * the CG schedule (0..2, see alofdft_set_cg_schedule) those launches ran, -1 if
- * none.  The first three pointers required. */
+/* Statistics of the sampled iterations for dtype 0 (FP64 CG) or 1 (FP32 inner CG of
+ * the refined solve): number of timed iterations, mean kernel time of one iteration
+ * in ms (all its launches), the grid points (n[0]*n[1]*n[2]) of the last timed one,
+ * and, for the non-null optional pointers, the CG schedule (0..2, see
+ * alofdft_set_cg_schedule; -1 if none) and the mean durations of the iteration's
+ * first (stencil) and second (update; 0 for schedule 2) launch.  The first three
+ * pointers required. */
 int alofdft_cg_kernel_stats(alofdft_ctx* ctx, int dtype, long long* launches, double* mean_ms, long long* points,
-                            int* schedule);
+                            int* schedule, double* first_ms, double* second_ms);
 
 /* ------------------------------------------------------------------ serving
  * A request loop that solves independent ground-state requests (systems of any
@@ -340,7 +390,8 @@ typedef struct {
   int queued, running;
   double p50_ms, p99_ms, mean_ms; /* submit-to-finish latency of completed requests */
   double solves_per_s;            /* completed / (last finish - first submit) */
-  double hbm_reserved_bytes;      /* footprint currently reserved by running requests */
+  double hbm_reserved_bytes;      /* footprints of running requests + arrays cached by the slots */
+  long long cancelled;            /* requests ended by alofdft_server_cancel or destroy */
 } alofdft_server_stats;
 
 /* Device memory (bytes) one request of this system reserves while it runs: the
@@ -367,7 +418,13 @@ int alofdft_server_poll(alofdft_server* srv, uint64_t ticket, alofdft_result* re
 
 int alofdft_server_get_stats(alofdft_server* srv, alofdft_server_stats* st);
 
-/* Waits for running and queued requests to finish, then stops the workers. */
+/* Cancels a request: a queued one is removed at once, a running one stops at its
+ * solve's next check (see alofdft_cancel); poll then returns ALOFDFT_CANCELLED.  A
+ * request that has finished keeps its result.  INVALID_ARGUMENT for an unknown ticket. */
+int alofdft_server_cancel(alofdft_server* srv, uint64_t ticket);
+
+/* Stops the server: queued requests are cancelled, running ones stop at their next
+ * check, then the workers exit and every slot's device memory is freed. */
 void alofdft_server_destroy(alofdft_server* srv);
 
 #ifdef __cplusplus

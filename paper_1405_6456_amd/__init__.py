@@ -16,8 +16,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libalofdft.so")
 
 OK, NOT_CONVERGED, PENDING = 0, 1, 2
-INVALID_ARGUMENT, OUT_OF_MEMORY, DEVICE_ERROR, NUMERICAL, REJECTED = -1, -2, -3, -4, -5
-AL, PENALTY = 0, 1
+INVALID_ARGUMENT, OUT_OF_MEMORY, DEVICE_ERROR, NUMERICAL, REJECTED, CANCELLED = -1, -2, -3, -4, -5, -6
+AL, PENALTY, LAGRANGE = 0, 1, 2
+PSEUDO_GAUSSIAN, PSEUDO_FD_LAPLACIAN = 0, 1
+GUESS_UNIFORM, GUESS_ATOMIC = 0, 1
+STOP_CONSTRAINT, STOP_ENERGY_CHANGE = 0, 1
 BC_ZERO, BC_MULTIPOLE = 0, 1
 FP64, FP32_REFINED = 0, 1
 
@@ -30,7 +33,9 @@ class Params(C.Structure):
                 ("phi_bc", C.c_int), ("precision", C.c_int), ("max_outer", C.c_int), ("max_inner", C.c_int),
                 ("max_cg", C.c_int), ("sigma0", C.c_double), ("max_secant", C.c_int),
                 ("secant_rel", C.c_double), ("restart_every", C.c_int), ("cg_check_every", C.c_int),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("pseudocharge", C.c_int), ("initial_guess", C.c_int),
+                ("guess_width", C.c_double), ("guess_floor", C.c_double), ("al_stop", C.c_int),
+                ("tol_energy", C.c_double)]
 
 
 class SystemS(C.Structure):
@@ -59,7 +64,8 @@ class Energy(C.Structure):
 class ServerStats(C.Structure):
     _fields_ = [(k, C.c_longlong) for k in ("submitted", "admitted", "completed", "rejected")] + \
                [("queued", C.c_int), ("running", C.c_int)] + \
-               [(k, C.c_double) for k in ("p50_ms", "p99_ms", "mean_ms", "solves_per_s", "hbm_reserved_bytes")]
+               [(k, C.c_double) for k in ("p50_ms", "p99_ms", "mean_ms", "solves_per_s", "hbm_reserved_bytes")] + \
+               [("cancelled", C.c_longlong)]
 
 
 class RelaxParams(C.Structure):
@@ -113,6 +119,7 @@ def lib():
         L.alofdft_energy_gradient.argtypes = [_VP, C.POINTER(SystemS), C.POINTER(Params), _VP, C.c_double,
                                               C.c_double, _VP, _VP, C.POINTER(Energy)]
         L.alofdft_pseudocharge.argtypes = [_VP, C.POINTER(SystemS), C.POINTER(Params), _VP, _DP]
+        L.alofdft_initial_guess.argtypes = [_VP, C.POINTER(SystemS), C.POINTER(Params), _VP]
         L.alofdft_forces.argtypes = [_VP, C.POINTER(SystemS), C.POINTER(Params), _VP, _DP]
         L.alofdft_bench_stencil.argtypes = [_VP, C.POINTER(C.c_int), C.c_int, C.c_int, C.c_int, C.c_int, _DP]
         L.alofdft_footprint_bytes.restype = C.c_size_t
@@ -121,11 +128,13 @@ def lib():
         L.alofdft_server_submit.argtypes = [_VP, C.POINTER(SystemS), C.POINTER(Params), C.POINTER(C.c_uint64)]
         L.alofdft_server_poll.argtypes = [_VP, C.c_uint64, C.POINTER(Result), _DP, _DP]
         L.alofdft_server_get_stats.argtypes = [_VP, C.POINTER(ServerStats)]
+        L.alofdft_server_cancel.argtypes = [_VP, C.c_uint64]
+        L.alofdft_cancel.argtypes = [_VP]
         L.alofdft_server_destroy.argtypes = [_VP]
         L.alofdft_server_destroy.restype = None
         L.alofdft_profile_cg_kernel.argtypes = [_VP, C.c_int]
         L.alofdft_cg_kernel_stats.argtypes = [_VP, C.c_int, C.POINTER(C.c_longlong), _DP, C.POINTER(C.c_longlong),
-                                              C.POINTER(C.c_int)]
+                                              C.POINTER(C.c_int), _DP, _DP]
         _lib = L
     return _lib
 
@@ -208,6 +217,11 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def cancel(self):
+        """Ask the call running on this context (from another thread) to stop; it raises
+        AlofdftError(CANCELLED).  With no call running, the next call stops at its first check."""
+        _check(self, lib().alofdft_cancel(self.handle))
 
     def set_tuning(self, variant=-1, target_blocks=0, inner_tol_exp=6):
         _check(self, lib().alofdft_set_tuning(self.handle, variant, target_blocks, inner_tol_exp))
@@ -328,6 +342,16 @@ class Context:
         _check(self, lib().alofdft_pseudocharge(self.handle, C.byref(S.s), C.byref(params), _ptr(b), C.byref(es)))
         return b, es.value
 
+    def initial_guess(self, system, params=None):
+        """The guess a solve takes without u0 (params.initial_guess), as a device tensor."""
+        import torch
+
+        params = params or default_params()
+        S = SystemArgs(system)
+        u = torch.empty(system.grid.shape, dtype=torch.float64, device=f"cuda:{self.device}")
+        _check(self, lib().alofdft_initial_guess(self.handle, C.byref(S.s), C.byref(params), _ptr(u)))
+        return u
+
     def forces(self, system, params, phi):
         params = params or default_params()
         S = SystemArgs(system)
@@ -340,12 +364,16 @@ class Context:
         """Start (reset) sampled HIP-event timing of the CG stencil kernel; 0 stops it."""
         _check(self, lib().alofdft_profile_cg_kernel(self.handle, int(sample_every)))
 
-    def cg_kernel_stats(self, dtype=0):
-        """(timed launches, mean ms per launch, grid points per launch, CG schedule of those
-        launches or -1) for dtype 0 (FP64) / 1 (FP32)."""
+    def cg_kernel_stats(self, dtype=0, split=False):
+        """(timed iterations, mean kernel ms per iteration, grid points, CG schedule or -1) for
+        dtype 0 (FP64) / 1 (FP32); with split=True also the mean ms of the iteration's first
+        (stencil) and second (update) launch."""
         n, ms, pts, sch = C.c_longlong(), C.c_double(), C.c_longlong(), C.c_int()
+        a, b = C.c_double(), C.c_double()
         _check(self, lib().alofdft_cg_kernel_stats(self.handle, dtype, C.byref(n), C.byref(ms), C.byref(pts),
-                                                   C.byref(sch)))
+                                                   C.byref(sch), C.byref(a), C.byref(b)))
+        if split:
+            return n.value, ms.value, pts.value, sch.value, a.value, b.value
         return n.value, ms.value, pts.value, sch.value
 
     def bench_stencil(self, n, fd_half_width=6, dtype=0, reps=100, nbuf=6):
@@ -420,6 +448,12 @@ class Server:
             if r is not None:
                 return r
             time.sleep(poll_s)
+
+    def cancel(self, ticket):
+        """Cancel a queued or running request (poll then reports status CANCELLED)."""
+        st = lib().alofdft_server_cancel(self.handle, ticket)
+        if st != OK:
+            raise AlofdftError(st, lib().alofdft_strerror(st).decode())
 
     def stats(self):
         s = ServerStats()

@@ -42,6 +42,7 @@ struct CGState {
   long long iter;  // iterations completed
   int done;        // 0 running, 1 converged, 2 non-finite, 3 zero rhs, 4 rounding breakdown
   int pad;
+  long long done_iter;  // iteration whose prologue set done (iter must still equal it at the end)
 };
 
 // Multipole moments of u^2 + b about the box centre and the constraint sum,
@@ -61,6 +62,7 @@ enum GradRed {
   G_XC,         // sum eps_xc u^2
   G_ES,         // sum (u^2 + b) phi
   G_U2,         // sum u^2
+  G_UG,         // sum u g   (Rayleigh quotient of the Lagrange-multiplier method)
   G_NRED
 };
 

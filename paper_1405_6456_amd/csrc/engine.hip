@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -36,6 +37,7 @@ struct alofdft_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
+  std::atomic<int> cancel{0};  // set by alofdft_cancel; the running solve stops at its next check
   std::map<std::string, std::pair<void*, size_t>> bufs;
   double* pin = nullptr;  // pinned host scalars
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -51,9 +53,18 @@ struct alofdft_ctx {
   int prof_every = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pool;
   long long prof_count[2] = {0, 0};
-  double prof_ms[2] = {0.0, 0.0};
+  double prof_ms[2] = {0.0, 0.0};      // kernel time of the sampled iterations (all their launches)
+  double prof_ms_first[2] = {0.0, 0.0};   // of their first launch (the stencil)
+  double prof_ms_second[2] = {0.0, 0.0};  // of their second launch (x and r update; schedules 0, 1)
   long long prof_points[2] = {0, 0};
   int prof_sched[2] = {-1, -1};  // CG schedule of the timed launches
+  // opt-in trace of every Poisson solve (ALOFDFT_TRACE=path at creation): one line per
+  // solve with the request's tag, its sequence number, the CG counts and verdicts, and
+  // exact hashes of the right-hand side and of phi before and after
+  bool trace = false;       // ALOFDFT_TRACE=path: counts, verdicts and the host sums of each evaluation
+  bool trace_hash = false;  // ALOFDFT_TRACE_HASH set as well: exact hashes of rhs and phi (syncs per solve)
+  uint64_t trace_tag = 0;
+  long long trace_seq = 0;
 };
 
 namespace {
@@ -90,7 +101,18 @@ void require(alofdft_ctx* c, bool ok, const char* msg) {
   }
 }
 
+// A pending cancellation ends the running call (checked at every host read of a CG
+// solve's state and at every nonlinear CG step); the flag is consumed.
+void check_cancel(alofdft_ctx* c) {
+  if (c && c->cancel.exchange(0)) {
+    set_err(c, "cancelled");
+    throw Fail{ALOFDFT_CANCELLED};
+  }
+}
+
 // ----------------------------------------------------------------- buffers
+void zero_bytes(alofdft_ctx* c, void* p, size_t bytes);
+
 void* buf(alofdft_ctx* c, const std::string& name, size_t bytes) {
   auto it = c->bufs.find(name);
   if (it != c->bufs.end()) {
@@ -99,8 +121,9 @@ void* buf(alofdft_ctx* c, const std::string& name, size_t bytes) {
     c->bufs.erase(it);
   }
   void* p = nullptr;
+  bytes = (bytes + 7) / 8 * 8;
   HIPC(c, hipMalloc(&p, bytes));
-  HIPC(c, hipMemsetAsync(p, 0, bytes, c->stream));
+  zero_bytes(c, p, bytes);
   c->bufs[name] = {p, bytes};
   return p;
 }
@@ -178,10 +201,14 @@ int launch_pw(alofdft_ctx* c, const Geom& g, const Op& op) {
 
 // Second half of a CG iteration: one row per wave, at most kPointwiseBlocks blocks.
 template <typename T>
-int launch_cg_update(alofdft_ctx* c, const Geom& g, const CGP2Op<T>& op) {
+int launch_cg_update(alofdft_ctx* c, const Geom& g, const CGP2Op<T>& op, hipEvent_t ev_start = nullptr,
+                     hipEvent_t ev_stop = nullptr) {
   const int rows = g.ny * g.nz;
   const int nb = std::max(1, std::min(kPointwiseBlocks, (rows + 3) / 4));
-  hipLaunchKernelGGL((k_cg_update<T, 256>), dim3(nb), dim3(256), 0, c->stream, g, op);
+  if (ev_start)  // the runtime stamps the events with the kernel's own start and end
+    hipExtLaunchKernelGGL((k_cg_update<T, 256>), dim3(nb), dim3(256), 0, c->stream, ev_start, ev_stop, 0, g, op);
+  else
+    hipLaunchKernelGGL((k_cg_update<T, 256>), dim3(nb), dim3(256), 0, c->stream, g, op);
   CHECK_LAUNCH(c);
   return nb;
 }
@@ -219,6 +246,13 @@ void fill(alofdft_ctx* c, T* a, long long n, T v) {
   const int nb = (int)std::min<long long>(2048, (n + 255) / 256);
   hipLaunchKernelGGL((k_fill<T>), dim3(std::max(nb, 1)), dim3(256), 0, c->stream, a, n, v);
   CHECK_LAUNCH(c);
+}
+
+// Device memory is cleared by a fill kernel on the context stream rather than by
+// hipMemsetAsync, so every clearing is an ordinary kernel of the stream (also for a caller
+// that captures the stream into a graph).  Bytes: a multiple of 8.
+void zero_bytes(alofdft_ctx* c, void* p, size_t bytes) {
+  fill<unsigned long long>(c, (unsigned long long*)p, (long long)(bytes / 8), 0ull);
 }
 // A padded work array whose halo and padding are zero for geometry g: zeroed
 // whenever it is first used with a geometry other than the last one.
@@ -301,6 +335,7 @@ struct CGResult {
   double relres = 0.0;
   int done = 0;
   int extra_mv = 0;  // stencil applications beyond one per iteration and the initial residual
+  int late = 0;      // a launch after the verdict updated the iterate (the final iteration != done_iter)
 };
 
 // Largest grid (nodes) on which the automatic schedule runs FP64 solves pipelined: the
@@ -390,7 +425,8 @@ CGResult cg_solve_pipe(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, cons
   double* partsI = bufT<double>(c, t + ".partsI", (size_t)std::max(maxsb, kPointwiseBlocks) * 2);
   double* pp[2] = {bufT<double>(c, t + ".partsC", (size_t)maxsb * 2), bufT<double>(c, t + ".partsD", (size_t)maxsb * 2)};
   CGState* st = bufT<CGState>(c, t + ".state", 1);
-  HIPC(c, hipMemsetAsync(st, 0, sizeof(CGState), c->stream));
+  static_assert(sizeof(CGState) % 8 == 0, "CGState is cleared in 8-byte words");
+  zero_bytes(c, st, sizeof(CGState));
   const double* prev = init_parts;
   int nprev = init_nparts;
   if (init) {
@@ -413,6 +449,7 @@ CGResult cg_solve_pipe(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, cons
       float ms = 0.f;
       HIPC(c, hipEventElapsedTime(&ms, c->prof_pool[pe.second].first, c->prof_pool[pe.second].second));
       c->prof_ms[pi] += ms;
+      c->prof_ms_first[pi] += ms;
       c->prof_count[pi]++;
       c->prof_points[pi] = (long long)g.nx * g.ny * g.nz;
       c->prof_sched[pi] = 2;
@@ -441,6 +478,7 @@ CGResult cg_solve_pipe(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, cons
     if (poll.due(k)) {
       HIPC(c, hipMemcpyAsync(c->pin, st, sizeof(CGState), hipMemcpyDeviceToHost, c->stream));
       sync(c);
+      check_cancel(c);
       const CGState* sp = (CGState*)c->pin;
       harvest(sp->done ? sp->iter : k + 1);
       if (sp->done) break;
@@ -471,6 +509,7 @@ CGResult cg_solve_pipe(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, cons
   CGResult res;
   res.done = s.done;
   res.extra_mv = 1;
+  res.late = s.done && s.iter != s.done_iter;
   if (s.done == 3) {
     fill<T>(c, x, g.total, T(0));
     return res;
@@ -502,7 +541,8 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
   double* partsA = bufT<double>(c, t + ".partsA", (size_t)maxsb);
   double* partsB = bufT<double>(c, t + ".partsB", (size_t)kPointwiseBlocks);
   CGState* st = bufT<CGState>(c, t + ".state", 1);
-  HIPC(c, hipMemsetAsync(st, 0, sizeof(CGState), c->stream));
+  static_assert(sizeof(CGState) % 8 == 0, "CGState is cleared in 8-byte words");
+  zero_bytes(c, st, sizeof(CGState));
   const double* prev = partsI;
   int nprev = 0;
   if (init) {
@@ -523,9 +563,12 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
   auto harvest = [&](long long stop_iter) {
     for (auto& pe : pending) {
       if (pe.first >= stop_iter) continue;
-      float ms = 0.f;
+      float ms = 0.f, ms2 = 0.f;
       HIPC(c, hipEventElapsedTime(&ms, c->prof_pool[pe.second].first, c->prof_pool[pe.second].second));
-      c->prof_ms[pi] += ms;
+      HIPC(c, hipEventElapsedTime(&ms2, c->prof_pool[pe.second + 1].first, c->prof_pool[pe.second + 1].second));
+      c->prof_ms[pi] += ms + ms2;
+      c->prof_ms_first[pi] += ms;
+      c->prof_ms_second[pi] += ms2;
       c->prof_count[pi]++;
       c->prof_points[pi] = (long long)g.nx * g.ny * g.nz;
       c->prof_sched[pi] = sched;
@@ -544,18 +587,25 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
     CGP1Op<T> op1{r, pold, pnew, Ap, st, prev, nprev, nred_prev, (int)k, tol2, partsA, T(0)};
     if (sched == 1) op1.pold = op1.pnew = p0;  // p and A p updated in place
     const bool timed = sampled(c, k);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (timed) std::tie(e0, e1) = prof_pair(c, pool_used);
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
+    if (timed) {  // both launches of the iteration carry a pair (pool entries pool_used, pool_used + 1)
+      std::tie(e0, e1) = prof_pair(c, pool_used);
+      std::tie(e2, e3) = prof_pair(c, pool_used + 1);
+    }
     const int nb1 = sched == 1 ? launch_stencil(c, g, A, CGP1LOp<T>{op1}, e0, e1)
                                         : launch_stencil(c, g, A, op1, e0, e1);  // events stamp the kernel itself
-    if (timed) pending.push_back({k, pool_used++});
     CGP2Op<T> op2{x, r, op1.pnew, Ap, st, partsA, nb1, (int)k, partsB, T(0)};
-    nprev = launch_cg_update(c, g, op2);
+    nprev = launch_cg_update(c, g, op2, e2, e3);
+    if (timed) {
+      pending.push_back({k, pool_used});
+      pool_used += 2;
+    }
     prev = partsB;
     nred_prev = 1;
     if (poll.due(k)) {
       HIPC(c, hipMemcpyAsync(c->pin, st, sizeof(CGState), hipMemcpyDeviceToHost, c->stream));
       sync(c);
+      check_cancel(c);
       const CGState* sp = (CGState*)c->pin;
       harvest(sp->done ? sp->iter : k + 1);
       if (sp->done) break;
@@ -593,6 +643,7 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
     s = *(CGState*)c->pin;
   }
   res.done = s.done;
+  res.late = s.done && s.iter != s.done_iter;
   if (s.done == 3) {  // zero right-hand side: the solution is zero
     fill<T>(c, x, g.total, T(0));
     res.iters = 0;
@@ -609,6 +660,9 @@ struct PoissonStats {
   long long iters = 0, mv64 = 0, mv32 = 0, refinements = 0;
   double relres = 0.0;
   int status = 0;
+  int restarts = 0;  // CG solves after the first (pipelined verification restarts)
+  int late = 0;      // CG solves in which a launch after the verdict updated the iterate
+  std::string verdicts;  // verdict and iterations of every CG solve, for the trace
 };
 
 // FP64 solve, or FP32 inner CG (FP64 dots) inside an FP64 iterative-refinement loop.
@@ -629,6 +683,13 @@ PoissonStats poisson(alofdft_ctx* c, const Geom& g, int fdn, double h, int preci
       ps.iters += r.iters;
       ps.mv64 += r.iters + 1 + r.extra_mv;
       ps.relres = r.relres;
+      ps.restarts = restart;
+      ps.late += r.late;
+      if (c->trace) {
+        char b[96];
+        std::snprintf(b, sizeof b, "%d:%lld:%.17g,", r.done, r.iters, r.relres);
+        ps.verdicts += b;
+      }
       const bool again = pipe && ((r.done == 1 && r.iters > 0) || r.done == 4);
       if (again && ps.iters < max_cg && restart < 7) continue;
       ps.status = r.done == 2 ? ALOFDFT_NUMERICAL : (r.done == 1 || r.done == 3 ? 0 : ALOFDFT_NOT_CONVERGED);
@@ -677,12 +738,44 @@ PoissonStats poisson(alofdft_ctx* c, const Geom& g, int fdn, double h, int preci
                                   partsF, nbf, true);
     ps.iters += ir.iters;
     ps.mv32 += ir.iters + ir.extra_mv;
+    ps.late += ir.late;
+    if (c->trace) ps.verdicts += std::to_string(ir.done) + ":" + std::to_string(ir.iters) + " ";
     if (ir.done == 2) { ps.status = ALOFDFT_NUMERICAL; return ps; }
     AddFloatOp add{x, x32, nullptr};
     launch_pw(c, g, add);
   }
   ps.status = ALOFDFT_NOT_CONVERGED;
   return ps;
+}
+
+// ----------------------------------------------------------------- trace
+std::mutex g_trace_mu;
+FILE* g_trace_file = nullptr;
+
+// FNV-1a hash of the interior bytes of a padded FP64 grid array (a host copy).
+uint64_t grid_hash(alofdft_ctx* c, const Geom& g, const double* a) {
+  std::vector<double> h((size_t)g.total);
+  HIPC(c, hipMemcpyAsync(h.data(), a, sizeof(double) * g.total, hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  uint64_t x = 1469598103934665603ull;
+  for (int k = 0; k < g.nz; ++k)
+    for (int j = 0; j < g.ny; ++j)
+      for (int i = 0; i < g.nx; ++i) {
+        uint64_t v;
+        std::memcpy(&v, &h[g.base + (size_t)k * g.plane + (size_t)j * g.px + i], 8);
+        for (int b = 0; b < 8; ++b) x = (x ^ ((v >> (8 * b)) & 0xff)) * 1099511628211ull;
+      }
+  return x;
+}
+
+void trace_line(const char* fmt, ...) {
+  std::lock_guard<std::mutex> lk(g_trace_mu);
+  if (!g_trace_file) return;
+  va_list ap;
+  va_start(ap, fmt);
+  std::vfprintf(g_trace_file, fmt, ap);
+  va_end(ap);
+  std::fflush(g_trace_file);
 }
 
 // ----------------------------------------------------------------- nuclei on the device
@@ -736,16 +829,52 @@ DevAtoms upload_atoms(alofdft_ctx* c, const alofdft_system* sys, double rc) {
   return d;
 }
 
-void pseudocharge_dev(alofdft_ctx* c, const Geom& g, const alofdft_system* sys, const DevAtoms& at, double s,
-                      double rc, double* b) {
+// Device description of b_J for the parameters: the Gaussian, or the discrete Laplacian of
+// V_J (Sec. 4) with the order-2n weights of the grid.
+PseudoDev pseudo_of(const alofdft_params* p, double h) {
+  PseudoDev P{};
+  P.mode = p->pseudocharge;
+  P.R = p->fd_half_width;
+  P.s = p->gauss_width;
+  P.rc = p->r_cut;
+  P.h = h;
+  double w[kMaxRadius + 1];
+  lap_weights(p->fd_half_width, h, w);
+  for (int q = 0; q <= kMaxRadius; ++q) P.w[q] = q <= p->fd_half_width ? w[q] : 0.0;
+  return P;
+}
+
+void pseudocharge_dev(alofdft_ctx* c, const Geom& g, const alofdft_system* sys, const DevAtoms& at,
+                      const PseudoDev& P, double* b) {
   fill<double>(c, b, g.total, 0.0);
   hipLaunchKernelGGL(k_pseudocharge, dim3(4096), dim3(256), 0, c->stream, g, sys->h, sys->origin[0], sys->origin[1],
-                     sys->origin[2], at.a, s, rc, b);
+                     sys->origin[2], at.a, P, b);
+  CHECK_LAUNCH(c);
+}
+
+// Superposition of atomic densities (Sec. 4) as the initial u, into a dense device
+// array: rho = sum_J Z_J (pi w^2)^(-3/2) exp(-r^2/w^2) (r <= 5w) + floor N/V, scaled to
+// h^3 sum rho = N, u = sqrt(rho).
+void atomic_guess_dev(alofdft_ctx* c, const alofdft_system* sys, const alofdft_params* prm, double* u_dense) {
+  const Geom g = make_geom(sys->n, prm->fd_half_width);
+  const double w = prm->guess_width;
+  const DevAtoms at = upload_atoms(c, sys, 5.0 * w);
+  double* rho = bufT<double>(c, "guess.rho", g.total);
+  const int nb = 1024;
+  double* parts = bufT<double>(c, "guess.parts", nb);
+  double* tot = bufT<double>(c, "guess.sum", 1);
+  const double h3 = sys->h * sys->h * sys->h;
+  const double floor_rho = prm->guess_floor * sys->N_elec / ((double)sys->n[0] * sys->n[1] * sys->n[2] * h3);
+  hipLaunchKernelGGL((k_atomic_density<256>), dim3(nb), dim3(256), 0, c->stream, g, sys->h, sys->origin[0],
+                     sys->origin[1], sys->origin[2], at.a, w, floor_rho, rho, parts);
+  CHECK_LAUNCH(c);
+  finalize(c, parts, nb, 1, 1.0, tot);
+  hipLaunchKernelGGL(k_density_to_u, dim3(2048), dim3(256), 0, c->stream, g, rho, tot, sys->N_elec, h3, u_dense);
   CHECK_LAUNCH(c);
 }
 
 // per-atom sums: self energy (phi == nullptr) or force sums (phi != nullptr)
-void atom_sums(alofdft_ctx* c, const Geom& g, const alofdft_system* sys, const DevAtoms& at, double s, double rc,
+void atom_sums(alofdft_ctx* c, const Geom& g, const alofdft_system* sys, const DevAtoms& at, const PseudoDev& P,
                int fdn, const double* phi, std::vector<double>* self, std::vector<double>* force) {
   const int M = sys->M;
   double* out = bufT<double>(c, "atoms.out", 4 * (size_t)M);
@@ -755,7 +884,7 @@ void atom_sums(alofdft_ctx* c, const Geom& g, const alofdft_system* sys, const D
   wt.c0 = 0.0;
   for (int p = 0; p <= kMaxRadius; ++p) wt.w[p] = p <= fdn ? w[p] : 0.0;
   hipLaunchKernelGGL((k_atom_sums<256>), dim3(M), dim3(256), 0, c->stream, g, sys->h, sys->origin[0],
-                     sys->origin[1], sys->origin[2], at.a, s, rc, wt, fdn, phi, self ? out : nullptr,
+                     sys->origin[1], sys->origin[2], at.a, P, wt, fdn, phi, self ? out : nullptr,
                      force ? out + M : nullptr);
   CHECK_LAUNCH(c);
   std::vector<double> host(4 * (size_t)M);
@@ -821,8 +950,17 @@ void validate(alofdft_ctx* c, const alofdft_system* s, const alofdft_params* p) 
   require(c, s->M >= 1 && s->R && s->Z, "need at least one atom");
   require(c, std::isfinite(s->N_elec) && s->N_elec > 0, "N must be > 0");
   require(c, p->lambda > 0 && p->gauss_width > 0 && p->r_cut > 0, "lambda, gauss_width, r_cut must be > 0");
-  require(c, p->method == ALOFDFT_METHOD_AUGMENTED_LAGRANGIAN || p->method == ALOFDFT_METHOD_PENALTY,
-          "method must be augmented Lagrangian or penalty");
+  require(c, p->method == ALOFDFT_METHOD_AUGMENTED_LAGRANGIAN || p->method == ALOFDFT_METHOD_PENALTY ||
+                 p->method == ALOFDFT_METHOD_LAGRANGE,
+          "method must be augmented Lagrangian, penalty or Lagrange multiplier");
+  require(c, p->pseudocharge == ALOFDFT_PSEUDO_GAUSSIAN || p->pseudocharge == ALOFDFT_PSEUDO_FD_LAPLACIAN,
+          "bad pseudocharge");
+  require(c, p->initial_guess == ALOFDFT_GUESS_UNIFORM || p->initial_guess == ALOFDFT_GUESS_ATOMIC,
+          "bad initial_guess");
+  require(c, p->initial_guess != ALOFDFT_GUESS_ATOMIC || (p->guess_width > 0 && p->guess_floor > 0),
+          "the atomic guess needs guess_width > 0 and guess_floor > 0");
+  require(c, p->al_stop == ALOFDFT_STOP_CONSTRAINT || (p->al_stop == ALOFDFT_STOP_ENERGY_CHANGE && p->tol_energy > 0),
+          "bad al_stop or tol_energy");
   require(c, p->mu0 > 0 && p->kappa > 0 && p->kappa < 1, "need mu0 > 0 and 0 < kappa < 1");
   require(c, p->phi_bc == ALOFDFT_BC_ZERO || p->phi_bc == ALOFDFT_BC_MULTIPOLE, "bad phi_bc");
   require(c, p->precision == ALOFDFT_FP64 || p->precision == ALOFDFT_FP32_REFINED, "bad precision");
@@ -838,6 +976,134 @@ void validate(alofdft_ctx* c, const alofdft_system* s, const alofdft_params* p) 
       require(c, x - p->r_cut >= lo - 1e-9 && x + p->r_cut <= hi + 1e-9, "an atom's r_cut ball leaves the box");
     }
   }
+}
+
+// ----------------------------------------------------------------- Lagrange-multiplier method (Sec. 5.3.2)
+// gp = g - eta u (the residual projected with the Rayleigh-quotient multiplier); reduces
+// gp.gp and gp.gp_old (Polak-Ribiere).
+struct LMResidualOp {
+  static constexpr int NRED = 2;
+  const double* g;
+  const double* u;
+  double* gp;
+  const double* gp_old;  // nullable (first step)
+  double eta;
+  double* parts_out;
+  template <int NT>
+  __device__ bool begin() { return true; }
+  __device__ void apply(long long i, int, int, int, double* red) const {
+    const double v = g[i] - eta * u[i];
+    gp[i] = v;
+    red[0] += v * v;
+    if (gp_old) red[1] += v * gp_old[i];
+  }
+};
+// d = -gp / M + beta d (constant Jacobi scaling M of the von Weizsaecker diagonal); reduces u.d.
+struct LMDirectionOp {
+  static constexpr int NRED = 1;
+  const double* gp;
+  const double* u;
+  double* d;
+  double inv_m, beta;
+  double* parts_out;
+  template <int NT>
+  __device__ bool begin() { return true; }
+  __device__ void apply(long long i, int, int, int, double* red) const {
+    const double dn = beta != 0.0 ? -gp[i] * inv_m + beta * d[i] : -gp[i] * inv_m;
+    d[i] = dn;
+    red[0] += u[i] * dn;
+  }
+};
+// d -= a u (d orthogonal to u); reduces g.d and d.d.
+struct LMProjectOp {
+  static constexpr int NRED = 2;
+  const double* g;
+  const double* u;
+  double* d;
+  double a;
+  double* parts_out;
+  template <int NT>
+  __device__ bool begin() { return true; }
+  __device__ void apply(long long i, int, int, int, double* red) const {
+    const double dn = d[i] - a * u[i];
+    d[i] = dn;
+    red[0] += g[i] * dn;
+    red[1] += dn * dn;
+  }
+};
+// u = |v| over the interior (the accepted point of a line search), reduces sum u^2.
+struct AbsOp {
+  static constexpr int NRED = 1;
+  double* u;
+  const double* v;
+  double scale;
+  double* parts_out;
+  template <int NT>
+  __device__ bool begin() { return true; }
+  __device__ void apply(long long i, int, int, int, double* red) const {
+    const double x = scale * fabs(v[i]);
+    u[i] = x;
+    red[0] += x * x;
+  }
+};
+
+// Minimum of f on [lo, hi] from an interior point x0 with f(x0) below both ends: Brent's
+// method (golden-section steps with parabolic interpolation through the three best
+// points, R. P. Brent, "Algorithms for Minimization without Derivatives", 1973, ch. 5).
+// Stops when the bracket is within 2 tol |x| + eps of the best point or after maxit
+// evaluations; returns the best point found.
+double brent_minimise(const std::function<double(double)>& f, double lo, double hi, double x0, double f0, double tol,
+                      int maxit) {
+  const double golden = 0.5 * (3.0 - std::sqrt(5.0));
+  double best = x0, fbest = f0;       // lowest value so far
+  double second = x0, fsecond = f0;   // second lowest
+  double third = x0, fthird = f0;     // previous value of second
+  double step = 0.0, prev_step = 0.0;
+  for (int it = 0; it < maxit; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    const double t1 = tol * std::fabs(best) + 1e-12, t2 = 2.0 * t1;
+    if (std::fabs(best - mid) <= t2 - 0.5 * (hi - lo)) break;
+    bool parabolic = false;
+    if (std::fabs(prev_step) > t1) {
+      // vertex of the parabola through (best, second, third), as best + p/q
+      const double r = (best - second) * (fbest - fthird);
+      double q = (best - third) * (fbest - fsecond);
+      double p = (best - third) * q - (best - second) * r;
+      q = 2.0 * (q - r);
+      if (q > 0.0) p = -p;
+      q = std::fabs(q);
+      const double keep = prev_step;
+      prev_step = step;
+      // accept only a step inside the bracket and shorter than half the step before last
+      if (std::fabs(p) < std::fabs(0.5 * q * keep) && p > q * (lo - best) && p < q * (hi - best)) {
+        step = p / q;
+        const double x = best + step;
+        if (x - lo < t2 || hi - x < t2) step = mid >= best ? t1 : -t1;
+        parabolic = true;
+      }
+    }
+    if (!parabolic) {
+      prev_step = best >= mid ? lo - best : hi - best;
+      step = golden * prev_step;
+    }
+    const double x = std::fabs(step) >= t1 ? best + step : best + (step > 0 ? t1 : -t1);
+    const double fx = f(x);
+    if (fx <= fbest) {
+      if (x >= best) lo = best; else hi = best;
+      third = second; fthird = fsecond;
+      second = best; fsecond = fbest;
+      best = x; fbest = fx;
+    } else {
+      if (x < best) lo = x; else hi = x;
+      if (fx <= fsecond || second == best) {
+        third = second; fthird = fsecond;
+        second = x; fsecond = fx;
+      } else if (fx <= fthird || third == best || third == second) {
+        third = x; fthird = fx;
+      }
+    }
+  }
+  return best;
 }
 
 // ----------------------------------------------------------------- the solver
@@ -889,9 +1155,10 @@ class Solver {
     for (double* a : {us_, v_, d_, sa_, sb_, b_, rhs_, ph_[0], ph_[1], ph_[2]}) fill<double>(c_, a, g_.total, 0.0);
     if (!warm_phi) fill<double>(c_, phi_, g_.total, 0.0);
     at_ = upload_atoms(c_, S_, P_->r_cut);
-    pseudocharge_dev(c_, g_, S_, at_, P_->gauss_width, P_->r_cut, b_);
+    pseudo_ = pseudo_of(P_, S_->h);
+    pseudocharge_dev(c_, g_, S_, at_, pseudo_, b_);
     std::vector<double> self;
-    atom_sums(c_, g_, S_, at_, P_->gauss_width, P_->r_cut, P_->fd_half_width, nullptr, &self, nullptr);
+    atom_sums(c_, g_, S_, at_, pseudo_, P_->fd_half_width, nullptr, &self, nullptr);
     E_self_ = 0.0;
     for (double x : self) E_self_ += 0.5 * h3_ * x;
     E_c_ = overlap_correction(S_, P_->gauss_width, nullptr);
@@ -942,10 +1209,28 @@ class Solver {
     lap_weights(P_->fd_half_width, S_->h, w);
     for (int p = 0; p <= kMaxRadius; ++p) rop.W.w[p] = p <= P_->fd_half_width ? w[p] : 0.0;
     launch_pw(c_, g_, rop);
+    uint64_t h_rhs = 0, h_phi0 = 0;
+    if (c_->trace_hash) {
+      h_rhs = grid_hash(c_, g_, rhs_);
+      h_phi0 = grid_hash(c_, g_, phi_);
+    }
+    unsigned long long* cks = nullptr;
+    if (c_->trace) {  // device checksums of rhs, phi before and phi after, read back with the sums
+      cks = bufT<unsigned long long>(c_, "trace.cks", 4);
+      fill<unsigned long long>(c_, cks, 4, 0ull);
+      hipLaunchKernelGGL(k_checksum, dim3(256), dim3(256), 0, c_->stream, g_, rhs_, cks);
+      hipLaunchKernelGGL(k_checksum, dim3(256), dim3(256), 0, c_->stream, g_, (const double*)phi_, cks + 1);
+      CHECK_LAUNCH(c_);
+    }
     auto t0 = std::chrono::steady_clock::now();
     PoissonStats ps = poisson(c_, g_, P_->fd_half_width, S_->h, P_->precision, rhs_, phi_, P_->tol_poisson,
                               P_->max_cg, P_->cg_check_every);
     auto t1 = std::chrono::steady_clock::now();
+    const uint64_t h_phi1 = c_->trace_hash ? grid_hash(c_, g_, phi_) : 0;
+    if (cks) {
+      hipLaunchKernelGGL(k_checksum, dim3(256), dim3(256), 0, c_->stream, g_, (const double*)phi_, cks + 2);
+      CHECK_LAUNCH(c_);
+    }
     time_poisson_ += std::chrono::duration<double, std::milli>(t1 - t0).count();
     counts_.poisson_solves++;
     counts_.cg_iters += ps.iters;
@@ -982,6 +1267,31 @@ class Solver {
     sync(c_);
     std::memcpy(ev.upd, c_->pin, sizeof(double) * kUpdRed);
     std::memcpy(ev.gr, c_->pin + kUpdRed, sizeof(double) * G_NRED);
+    if (c_->trace) {
+      // the density moments that fixed the right-hand side, the Poisson solve, and the
+      // sums of the evaluation that used its phi, all as exact bit patterns
+      std::string sums;
+      char b[24];
+      for (int i = 0; i < kUpdRed; ++i) {
+        std::snprintf(b, sizeof b, "%016llx", (unsigned long long)__builtin_bit_cast(uint64_t, ev.upd[i]));
+        sums += i ? "," : "";
+        sums += b;
+      }
+      sums += " gr ";
+      for (int i = 0; i < G_NRED; ++i) {
+        std::snprintf(b, sizeof b, "%016llx", (unsigned long long)__builtin_bit_cast(uint64_t, ev.gr[i]));
+        sums += i ? "," : "";
+        sums += b;
+      }
+      unsigned long long ck[3];
+      HIPC(c_, hipMemcpyAsync(ck, cks, sizeof ck, hipMemcpyDeviceToHost, c_->stream));
+      sync(c_);
+      trace_line("ctx %p tag %016llx seq %lld prec %d iters %lld restarts %d late %d relres %.17g rhs %016llx "
+                 "phi0 %016llx phi1 %016llx ckrhs %016llx ckphi0 %016llx ckphi1 %016llx cg %s upd %s\n",
+                 (void*)c_, (unsigned long long)c_->trace_tag, c_->trace_seq++, P_->precision, ps.iters, ps.restarts,
+                 ps.late, ps.relres, (unsigned long long)h_rhs, (unsigned long long)h_phi0,
+                 (unsigned long long)h_phi1, ck[0], ck[1], ck[2], ps.verdicts.c_str(), sums.c_str());
+    }
     time_grad_ += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
     counts_.grad_evals++;
     counts_.matvec_fp64++;
@@ -1039,6 +1349,7 @@ class Solver {
     its = 0;
     double gd_unsigned = cur.gr[G_GD];
     for (;;) {
+      check_cancel(c_);
       if (!std::isfinite(gn)) { status = ALOFDFT_NUMERICAL; break; }
       if (gn < P_->tol_grad) { status = 0; break; }
       if (its >= P_->max_inner) { status = 1; break; }
@@ -1126,15 +1437,150 @@ class Solver {
   int run(alofdft_result* res) {
     auto t0 = std::chrono::steady_clock::now();
     counts_ = alofdft_counts{};
-    // v = u0 (t = 0 trial from u_start = u0, d = 0)
     Eval cur;
+    int status = ALOFDFT_NOT_CONVERGED;
+    double gn = 0.0, dE = 0.0, eta = 0.0, eta_star = 0.0;
+    if (P_->method == ALOFDFT_METHOD_LAGRANGE) {
+      status = lagrange(cur, eta_star, gn);
+      time_setup_ = 0.0;
+    } else {
+      status = augmented_lagrangian(cur, eta_star, gn, dE, t0);
+    }
+    if (status == ALOFDFT_OK && poisson_capped_) status = ALOFDFT_NOT_CONVERGED;
+    (void)eta;
+    return finish(res, cur, status, eta_star, dE, gn);
+  }
+
+  // Host sums of a pointwise pass: finalize the block partials (scaled by scale) and copy
+  // the first n to the host.
+  template <class Op>
+  void reduce_pw(const Op& op, int n, double scale, double* out) {
+    const int nb = launch_pw(c_, g_, op);
+    double* dst = scal_ + kUpdRed + G_NRED;
+    finalize(c_, op.parts_out, nb, Op::NRED, scale, dst);
+    HIPC(c_, hipMemcpyAsync(c_->pin, dst, sizeof(double) * n, hipMemcpyDeviceToHost, c_->stream));
+    sync(c_);
+    std::memcpy(out, c_->pin, sizeof(double) * n);
+  }
+
+  // Lagrange-multiplier method (Sec. 5.3.2): u stays on h^3 sum u^2 = N, the multiplier is
+  // the Rayleigh quotient eta = h^3 u.g / N of the residual g = H u (no multiplier terms),
+  // Polak-Ribiere directions built from gp = g - eta u are projected orthogonal to u, and
+  // each step minimises the energy along the great circle u cos t + sqrt(N) d sin t
+  // (d normalised to h^3 d.d = 1) with Brent's method.  Converged at ||gp|| < tol_grad.
+  int lagrange(Eval& cur, double& eta, double& gn) {
+    const double Ne = S_->N_elec, sN = std::sqrt(Ne);
+    const double M = vw_diag_;  // constant Jacobi scaling (diagonal of -(lambda/2) Delta_h)
+    double* g = gridbuf<double>(c_, "lm.g", g_);
+    double* gpb[2] = {gridbuf<double>(c_, "lm.gp0", g_), gridbuf<double>(c_, "lm.gp1", g_)};
+    double* parts = bufT<double>(c_, "lm.parts", (size_t)kPointwiseBlocks * 2);
+    gout_ = g;
+    // start on the constraint surface: u = |u0| sqrt(N / h^3 sum u0^2)
+    double nrm;
+    reduce_pw(AbsOp{us_, us_, 1.0, parts}, 1, h3_, &nrm);
+    require(c_, nrm > 0 && std::isfinite(nrm), "the initial guess has no finite norm");
+    reduce_pw(AbsOp{us_, us_, std::sqrt(Ne / nrm), parts}, 1, h3_, &nrm);
+    double* zero = zero_dir();
+    auto eval_at = [&](double a, double t, Eval& ev) {  // v = a u + t d, energies and residual at |v|
+      TrialOp op{us_, t == 0.0 ? zero : d_, b_, v_, t, frame_, partsU_};
+      op.a = a;
+      nU_ = launch_pw(c_, g_, op);
+      bad_ = false;
+      eval_at_v(0.0, 0.0, ev);
+    };
+    double delta_new = 1.0;
+    int status = ALOFDFT_NOT_CONVERGED, since_restart = 0, cur_gp = 0;
+    long long it = 0;
+    for (;;) {
+      check_cancel(c_);
+      eval_at(1.0, 0.0, cur);
+      require_finite("the residual of the Lagrange-multiplier method");
+      eta = h3_ * cur.gr[G_UG] / Ne;
+      double sums[2];
+      reduce_pw(LMResidualOp{g, us_, gpb[cur_gp], it > 0 ? gpb[cur_gp ^ 1] : nullptr, eta, parts}, 2, 1.0, sums);
+      gn = std::sqrt(h3_ * sums[0]);
+      if (!std::isfinite(gn)) { status = ALOFDFT_NUMERICAL; break; }
+      if (gn < P_->tol_grad) { status = ALOFDFT_OK; break; }
+      if (it >= P_->max_inner) break;
+      const double delta_old = delta_new, delta_mid = sums[1] / M;
+      delta_new = sums[0] / M;
+      double beta = it == 0 ? 0.0 : (delta_new - delta_mid) / delta_old;
+      ++since_restart;
+      if (it == 0 || beta <= 0.0 || since_restart >= P_->restart_every) {
+        beta = 0.0;
+        since_restart = 0;
+      }
+      double ud, gd[2];
+      reduce_pw(LMDirectionOp{gpb[cur_gp], us_, d_, 1.0 / M, beta, parts}, 1, h3_, &ud);
+      reduce_pw(LMProjectOp{g, us_, d_, ud / Ne, parts}, 2, h3_, gd);
+      if (gd[0] >= 0.0) {  // not a descent direction: steepest descent
+        reduce_pw(LMDirectionOp{gpb[cur_gp], us_, d_, 1.0 / M, 0.0, parts}, 1, h3_, &ud);
+        reduce_pw(LMProjectOp{g, us_, d_, ud / Ne, parts}, 2, h3_, gd);
+        since_restart = 0;
+      }
+      const double dn = std::sqrt(gd[1]);
+      const double E0 = energy(cur);
+      // energy along the circle: u(t) = u cos t + sqrt(N) (d/dn) sin t
+      Eval ev;
+      auto E_at = [&](double t) {
+        eval_at(std::cos(t), sN * std::sin(t) / dn, ev);
+        return bad_ ? HUGE_VAL : energy(ev);
+      };
+      const double slope = 2.0 * sN * gd[0] / dn;  // dE/dt at t = 0
+      double ta = 0.0, tb = std::min(0.5, std::fabs(slope) / (2.0 * M * Ne) + 1e-6), fb = E_at(tb), tc, fc;
+      bool bracketed = true;
+      if (fb > E0) {  // shorten the probe until it lies below E0
+        tc = tb;
+        int guard = 0;
+        do {
+          tb *= 0.5;
+          fb = E_at(tb);
+          if (fb > E0) tc = tb;
+        } while (fb > E0 && ++guard < 40);
+        bracketed = fb <= E0;
+      } else {  // lengthen it while the energy falls
+        tc = 2.0 * tb;
+        fc = E_at(tc);
+        int guard = 0;
+        while (fc < fb && ++guard < 40) {
+          ta = tb;
+          tb = tc;
+          fb = fc;
+          tc *= 2.0;
+          fc = E_at(tc);
+        }
+      }
+      if (!bracketed) break;  // no lower energy along the direction: rounding floor
+      const double t = brent_minimise(E_at, ta, tc, tb, fb, 1e-8, 60);
+      // accept: u = |u cos t + sqrt(N) dhat sin t|
+      TrialOp op{us_, d_, b_, v_, sN * std::sin(t) / dn, frame_, partsU_};
+      op.a = std::cos(t);
+      launch_pw(c_, g_, op);
+      reduce_pw(AbsOp{us_, v_, 1.0, parts}, 1, h3_, &nrm);
+      cur_gp ^= 1;
+      ++it;
+      if (c_->progress && it % 20 == 0)
+        std::fprintf(stderr, "alofdft: Lagrange step %lld |g - eta u| %.3e E %.12f eta %.10f\n", it, gn, E0, eta);
+    }
+    counts_.outer = 1;
+    counts_.inner = it;
+    gout_ = nullptr;
+    return status;
+  }
+
+  // Algorithm AugLag (Sec. 3) around the nonlinear CG inner solver; the penalty method
+  // (Sec. 5.3.2) is the same loop with eta fixed at 0.
+  int augmented_lagrangian(Eval& cur, double& eta_star, double& gn, double& dE,
+                           std::chrono::steady_clock::time_point t0) {
+    // v = u0 (t = 0 trial from u_start = u0, d = 0)
     double eta = P_->method == ALOFDFT_METHOD_PENALTY ? 0.0 : P_->eta0;
     double mu = P_->mu0;
     eval_trial(0.0, eta, mu, false, 0.0, cur);
     require_finite("the residual at the initial guess");
     time_setup_ = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     int status = ALOFDFT_NOT_CONVERGED;
-    double E_prev = 0.0, gn = 0.0, dE = 0.0, eta_star = eta;
+    double E_prev = 0.0;
+    eta_star = eta;
     for (int q = 0; q < P_->max_outer; ++q) {
       if (q > 0) eval_at_v_refresh(eta, mu, cur);  // same u, new eta/mu: recompute residual terms
       long long its = 0;
@@ -1153,16 +1599,24 @@ class Solver {
       if (c_->progress)
         std::fprintf(stderr, "alofdft: AL step %d E %.12f C_h/N %.3e nlcg %lld cg %lld\n", q + 1, E,
                      std::fabs(C) / S_->N_elec, its, counts_.cg_iters);
-      if (std::fabs(C) / S_->N_elec < P_->tol_constraint && st == 0) {
+      // the workloads stop on the constraint; Algorithm AugLag itself on the energy change
+      const bool stop = P_->al_stop == ALOFDFT_STOP_ENERGY_CHANGE
+                            ? (q > 0 && std::fabs(dE) / S_->M < P_->tol_energy)
+                            : std::fabs(C) / S_->N_elec < P_->tol_constraint;
+      if (stop && st == 0) {
         status = ALOFDFT_OK;
         break;
       }
       eta = P_->method == ALOFDFT_METHOD_PENALTY ? 0.0 : eta_star;
       mu *= P_->kappa;
     }
-    if (status == ALOFDFT_OK && poisson_capped_) status = ALOFDFT_NOT_CONVERGED;
+    return status;
+  }
+
+  int finish(alofdft_result* res, const Eval& cur, int status, double eta_star, double dE, double gn) {
     alofdft_energy en;
     energy(cur, &en);
+    en.grad_norm = gn;  // the inner solver's residual norm (for the Lagrange method, of g - eta u)
     res->E_total = en.E_total;
     res->E_TF = en.E_TF;
     res->E_vW = en.E_vW;
@@ -1208,7 +1662,7 @@ class Solver {
 
   void forces(double* out) {
     std::vector<double> f, fc;
-    atom_sums(c_, g_, S_, at_, P_->gauss_width, P_->r_cut, P_->fd_half_width, phi_, nullptr, &f);
+    atom_sums(c_, g_, S_, at_, pseudo_, P_->fd_half_width, phi_, nullptr, &f);
     overlap_correction(S_, P_->gauss_width, &fc);
     for (int i = 0; i < 3 * S_->M; ++i) out[i] = h3_ * f[i] + fc[i];
   }
@@ -1244,6 +1698,7 @@ class Solver {
   StencilW<double> Wlap_;
   BoxFrame frame_;
   DevAtoms at_;
+  PseudoDev pseudo_{};
   double E_self_ = 0.0, E_c_ = 0.0;
   alofdft_counts counts_{};
   double relres_ = 0.0;
@@ -1306,11 +1761,29 @@ int solve_impl(alofdft_ctx* c, const alofdft_system* sys, const alofdft_params* 
   double* u0 = bufT<double>(c, "io.u0", (size_t)n);
   if (u0_dev) {
     HIPC(c, hipMemcpyAsync(u0, u0_dev, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+  } else if (!u0_host && prm->initial_guess == ALOFDFT_GUESS_ATOMIC) {
+    atomic_guess_dev(c, sys, prm, u0);
   } else {
     std::vector<double> h = u0_host ? std::vector<double>(u0_host, u0_host + n) : default_u0(sys, prm->seed);
     for (double x : h) require(c, std::isfinite(x), "non-finite initial guess");
     HIPC(c, hipMemcpyAsync(u0, h.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
     sync(c);
+  }
+  if (c->trace) {
+    // tag: hash of the system and the parameters that shape the solve
+    uint64_t x = 1469598103934665603ull;
+    auto mix = [&](const void* p, size_t n) {
+      const unsigned char* b = (const unsigned char*)p;
+      for (size_t i = 0; i < n; ++i) x = (x ^ b[i]) * 1099511628211ull;
+    };
+    mix(sys->n, sizeof(sys->n));
+    mix(&sys->h, sizeof(double));
+    mix(sys->origin, sizeof(sys->origin));
+    mix(sys->R, sizeof(double) * 3 * sys->M);
+    mix(sys->Z, sizeof(double) * sys->M);
+    mix(&prm->precision, sizeof(int));
+    c->trace_tag = x;
+    c->trace_seq = 0;
   }
   Solver S(c, sys, prm);
   S.setup(u0, true, warm_phi);
@@ -1436,7 +1909,9 @@ size_t footprint(const alofdft_system* s, const alofdft_params* p) {
   const size_t n = (size_t)s->n[0] * s->n[1] * s->n[2];
   // solver arrays (12), FP64 CG (7: every schedule's work arrays), refinement residual (1): double;
   // FP32 CG (7) + correction (1): float
-  const size_t arrays = (12 + 7 + 1) * 8 * T + (7 + 1) * 4 * T;
+  // (+3 for the Lagrange method's residual arrays, +1 for the atomic guess's density)
+  const size_t extra = (p->method == ALOFDFT_METHOD_LAGRANGE ? 3 : 0) + (p->initial_guess == ALOFDFT_GUESS_ATOMIC ? 1 : 0);
+  const size_t arrays = (12 + 7 + 1 + extra) * 8 * T + (7 + 1) * 4 * T;
   const size_t dense = 3 * 8 * n;  // initial guess, u and phi outputs
   // block partials, scalars, atom arrays and the cell list (with slack)
   const size_t small = (size_t)(max_stencil_blocks(g, 4096) + 4 * kPointwiseBlocks) * 16 * 8 + 128 * (size_t)s->M +
@@ -1465,6 +1940,7 @@ struct Request {
   size_t fp = 0;
   std::chrono::steady_clock::time_point t_submit, t_start, t_end;
   int status = ALOFDFT_PENDING;
+  int slot = -1;  // slot running it, -1 while queued
   alofdft_result res{};
   std::vector<double> u, forces;
 };
@@ -1476,17 +1952,19 @@ struct alofdft_server {
   size_t budget = 0;
   std::vector<alofdft_ctx*> ctx;
   std::vector<hipStream_t> streams;
-  std::vector<size_t> held;  // bytes each slot's context holds
+  std::vector<size_t> held;  // bytes of cached work arrays each slot's context holds
+  std::vector<std::shared_ptr<Request>> current;  // request each slot runs (null when idle)
   std::vector<std::thread> workers;
   std::mutex mu;
   std::condition_variable cv;
   std::deque<std::shared_ptr<Request>> queue;
   std::map<uint64_t, std::shared_ptr<Request>> reqs;
-  size_t reserved = 0;  // footprints of running requests beyond what their slots already hold
+  size_t reserved = 0;  // footprints of the running requests
+  bool trim = false;    // the front request does not fit: idle slots drop their cached arrays
   int running = 0;
   bool stop = false;
   uint64_t next_id = 1;
-  long long submitted = 0, admitted = 0, completed = 0, rejected = 0;
+  long long submitted = 0, admitted = 0, completed = 0, rejected = 0, cancelled = 0;
   std::vector<double> lat_ms;
   bool have_first = false;
   std::chrono::steady_clock::time_point first_submit, last_end;
@@ -1494,10 +1972,14 @@ struct alofdft_server {
 
 namespace {
 
-// Bytes in use on the device if slot w takes a request of footprint fp.
-size_t demand(const alofdft_server* s, int w, size_t fp) {
-  size_t tot = s->reserved;
-  for (size_t i = 0; i < s->held.size(); ++i) tot += (int)i == w ? std::max(s->held[i], fp) : s->held[i];
+// Device bytes the server may occupy if a request of footprint fp is admitted: every
+// slot's cached arrays, the full footprint of every running request, and fp.  Cached
+// arrays the request may reuse are counted twice, so the bound is conservative; a request
+// that does not fit makes the idle slots drop their caches (trim), after which it fits as
+// soon as the running requests leave room (fp alone never exceeds the budget).
+size_t demand(const alofdft_server* s, size_t fp) {
+  size_t tot = s->reserved + fp;
+  for (size_t h : s->held) tot += h;
   return tot;
 }
 
@@ -1511,19 +1993,30 @@ void worker_loop(alofdft_server* s, int w) {
       for (;;) {
         if (s->stop && s->queue.empty()) return;
         if (!s->queue.empty()) {
-          const size_t fp = s->queue.front()->fp;
-          if (demand(s, w, fp) <= s->budget) break;
-          if (s->held[w] > fp) {  // this idle slot's cached arrays are in the way: drop them
-            free_all(c);
-            s->held[w] = 0;
-            if (demand(s, w, fp) <= s->budget) break;
+          if (demand(s, s->queue.front()->fp) <= s->budget) break;
+          if (!s->trim) {
+            s->trim = true;
+            s->cv.notify_all();  // wake the other idle slots to drop their caches too
           }
+        }
+        if (s->trim && s->held[w] > 0) {
+          // drop this idle slot's cached arrays; they count in the demand until freed
+          lk.unlock();
+          free_all(c);
+          lk.lock();
+          s->held[w] = 0;
+          s->cv.notify_all();
+          continue;
         }
         s->cv.wait(lk);
       }
       r = s->queue.front();
       s->queue.pop_front();
-      s->reserved += r->fp > s->held[w] ? r->fp - s->held[w] : 0;
+      s->trim = false;
+      s->reserved += r->fp;
+      r->slot = w;
+      s->current[w] = r;
+      c->cancel.store(0);  // a cancellation meant for the previous request on this slot
       s->running++;
       s->admitted++;
     }
@@ -1541,15 +2034,19 @@ void worker_loop(alofdft_server* s, int w) {
     r->t_end = std::chrono::steady_clock::now();
     {
       std::lock_guard<std::mutex> lk(s->mu);
-      const size_t before = s->held[w];
       s->held[w] = held_bytes(c);
-      s->reserved -= r->fp > before ? r->fp - before : 0;
+      s->reserved -= r->fp;
+      s->current[w] = nullptr;
       s->running--;
-      s->completed++;
       r->status = st;
       r->res.status = st;
-      s->lat_ms.push_back(std::chrono::duration<double, std::milli>(r->t_end - r->t_submit).count());
-      s->last_end = r->t_end;
+      if (st == ALOFDFT_CANCELLED) {
+        s->cancelled++;
+      } else {
+        s->completed++;
+        s->lat_ms.push_back(std::chrono::duration<double, std::milli>(r->t_end - r->t_submit).count());
+        s->last_end = r->t_end;
+      }
     }
     s->cv.notify_all();
   }
@@ -1569,6 +2066,7 @@ const char* alofdft_strerror(int s) {
     case ALOFDFT_DEVICE_ERROR: return "device error";
     case ALOFDFT_NUMERICAL: return "non-finite value";
     case ALOFDFT_REJECTED: return "rejected";
+    case ALOFDFT_CANCELLED: return "cancelled";
   }
   return "unknown status";
 }
@@ -1601,6 +2099,12 @@ int alofdft_default_params(alofdft_params* p) {
   p->restart_every = 50;
   p->cg_check_every = kCheckEvery;
   p->seed = 6456;
+  p->pseudocharge = ALOFDFT_PSEUDO_GAUSSIAN;
+  p->initial_guess = ALOFDFT_GUESS_UNIFORM;
+  p->guess_width = 1.5;
+  p->guess_floor = 1e-3;
+  p->al_stop = ALOFDFT_STOP_CONSTRAINT;
+  p->tol_energy = 3.6749e-6;
   return ALOFDFT_OK;
 }
 
@@ -1614,6 +2118,12 @@ int alofdft_create(alofdft_ctx** out, int hip_device, void* hip_stream) {
   c->device = hip_device;
   c->stream = (hipStream_t)hip_stream;
   c->progress = std::getenv("ALOFDFT_PROGRESS") != nullptr;
+  if (const char* tp = std::getenv("ALOFDFT_TRACE")) {
+    std::lock_guard<std::mutex> lk(g_trace_mu);
+    if (!g_trace_file) g_trace_file = std::fopen(tp, "a");
+    c->trace = g_trace_file != nullptr;
+    c->trace_hash = c->trace && std::getenv("ALOFDFT_TRACE_HASH") != nullptr;
+  }
   int st = guarded(c, [&]() {
     HIPC(c, hipHostMalloc((void**)&c->pin, 4096, hipHostMallocDefault));
     HIPC(c, hipEventCreate(&c->ev0));
@@ -1665,6 +2175,8 @@ int alofdft_profile_cg_kernel(alofdft_ctx* c, int sample_every) {
   for (int i = 0; i < 2; ++i) {
     c->prof_count[i] = 0;
     c->prof_ms[i] = 0.0;
+    c->prof_ms_first[i] = 0.0;
+    c->prof_ms_second[i] = 0.0;
     c->prof_points[i] = 0;
     c->prof_sched[i] = -1;
   }
@@ -1672,11 +2184,14 @@ int alofdft_profile_cg_kernel(alofdft_ctx* c, int sample_every) {
 }
 
 int alofdft_cg_kernel_stats(alofdft_ctx* c, int dtype, long long* launches, double* mean_ms, long long* points,
-                            int* schedule) {
+                            int* schedule, double* first_ms, double* second_ms) {
   if (!c || (dtype != 0 && dtype != 1) || !launches || !mean_ms || !points) return ALOFDFT_INVALID_ARGUMENT;
   if (schedule) *schedule = c->prof_sched[dtype];
-  *launches = c->prof_count[dtype];
-  *mean_ms = c->prof_count[dtype] ? c->prof_ms[dtype] / c->prof_count[dtype] : 0.0;
+  const long long n = c->prof_count[dtype];
+  *launches = n;
+  *mean_ms = n ? c->prof_ms[dtype] / n : 0.0;
+  if (first_ms) *first_ms = n ? c->prof_ms_first[dtype] / n : 0.0;
+  if (second_ms) *second_ms = n ? c->prof_ms_second[dtype] / n : 0.0;
   *points = c->prof_points[dtype];
   return ALOFDFT_OK;
 }
@@ -1817,6 +2332,23 @@ int alofdft_energy_gradient(alofdft_ctx* c, const alofdft_system* sys, const alo
   });
 }
 
+int alofdft_initial_guess(alofdft_ctx* c, const alofdft_system* sys, const alofdft_params* prm, double* u0) {
+  if (!c) return ALOFDFT_INVALID_ARGUMENT;
+  return guarded(c, [&]() {
+    require(c, u0 != nullptr, "null argument");
+    validate(c, sys, prm);
+    const long long n = npoints(sys->n);
+    if (prm->initial_guess == ALOFDFT_GUESS_ATOMIC) {
+      atomic_guess_dev(c, sys, prm, u0);
+    } else {
+      std::vector<double> h = default_u0(sys, prm->seed);
+      HIPC(c, hipMemcpyAsync(u0, h.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+    }
+    sync(c);
+    return ALOFDFT_OK;
+  });
+}
+
 int alofdft_pseudocharge(alofdft_ctx* c, const alofdft_system* sys, const alofdft_params* prm, double* b,
                          double* self_energy) {
   if (!c) return ALOFDFT_INVALID_ARGUMENT;
@@ -1916,6 +2448,7 @@ int alofdft_server_create(alofdft_server** out, int hip_device, size_t hbm_budge
     }
     s->ctx.push_back(c);
     s->held.push_back(0);
+    s->current.push_back(nullptr);
   }
   for (int w = 0; w < max_slots; ++w) s->workers.emplace_back(worker_loop, s, w);
   *out = s;
@@ -1984,6 +2517,7 @@ int alofdft_server_get_stats(alofdft_server* s, alofdft_server_stats* st) {
   st->admitted = s->admitted;
   st->completed = s->completed;
   st->rejected = s->rejected;
+  st->cancelled = s->cancelled;
   st->queued = (int)s->queue.size();
   st->running = s->running;
   size_t hb = s->reserved;
@@ -2007,11 +2541,49 @@ int alofdft_server_get_stats(alofdft_server* s, alofdft_server_stats* st) {
   return ALOFDFT_OK;
 }
 
+int alofdft_server_cancel(alofdft_server* s, uint64_t ticket) {
+  if (!s) return ALOFDFT_INVALID_ARGUMENT;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return ALOFDFT_INVALID_ARGUMENT;
+  Request& r = *it->second;
+  if (r.status != ALOFDFT_PENDING) return ALOFDFT_OK;  // finished already: its result stays
+  if (r.slot < 0) {
+    for (auto q = s->queue.begin(); q != s->queue.end(); ++q)
+      if ((*q)->id == ticket) {
+        s->queue.erase(q);
+        break;
+      }
+    r.status = ALOFDFT_CANCELLED;
+    r.res.status = ALOFDFT_CANCELLED;
+    s->cancelled++;
+    s->cv.notify_all();  // the next request may fit now
+  } else {
+    s->ctx[r.slot]->cancel.store(1);  // the slot's solve stops at its next check
+  }
+  return ALOFDFT_OK;
+}
+
+int alofdft_cancel(alofdft_ctx* c) {
+  if (!c) return ALOFDFT_INVALID_ARGUMENT;
+  c->cancel.store(1);
+  return ALOFDFT_OK;
+}
+
 void alofdft_server_destroy(alofdft_server* s) {
   if (!s) return;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     s->stop = true;
+    // queued requests are cancelled, running ones stop at their next check
+    for (auto& q : s->queue) {
+      q->status = ALOFDFT_CANCELLED;
+      q->res.status = ALOFDFT_CANCELLED;
+      s->cancelled++;
+    }
+    s->queue.clear();
+    for (size_t w = 0; w < s->current.size(); ++w)
+      if (s->current[w]) s->ctx[w]->cancel.store(1);
   }
   s->cv.notify_all();
   for (auto& t : s->workers)

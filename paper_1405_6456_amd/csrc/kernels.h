@@ -23,6 +23,17 @@
 
 namespace alofdft {
 
+// ----------------------------------------------------------------- values written by other blocks
+// The CG scalars, finalized sums and block partials are written by one block (of this
+// launch, for the verdict flag, or of an earlier one) and read by all: they are read with
+// an agent-scope atomic load, a vector load that is coherent with other blocks' writes and
+// well defined while another block of the same launch writes the value (a plain load at a
+// wave-uniform address would go through the scalar data cache).
+template <typename T>
+__device__ inline T ld_dev(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ----------------------------------------------------------------- reductions
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -68,7 +79,7 @@ __device__ inline double block_sum_parts(const double* parts, int n, int stride,
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int b = b0 + u * NT;
-      v[u] = b < n ? parts[(long long)b * stride + comp] : 0.0;
+      v[u] = b < n ? ld_dev(parts + (long long)b * stride + comp) : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) s += v[u];
@@ -84,6 +95,18 @@ __device__ inline double block_sum_parts(const double* parts, int n, int stride,
 }
 
 __device__ inline bool is_block0_thread0() { return blockIdx.x == 0 && threadIdx.x == 0; }
+
+// The CG verdict flag is written by block 0 of a launch while the other blocks of the same
+// launch run.  A block reads it once and shares it through LDS, so all its waves take the
+// same branch: a wave that returned on a fresh flag while its siblings, which read the old
+// one, waited at the next barrier of the prologue's reduction would release that barrier
+// early and the siblings would sum per-wave partials that were never written.
+__device__ inline int block_read_done(const CGState* st) {
+  __shared__ int flag;
+  if (threadIdx.x == 0) flag = ld_dev(&st->done);
+  __syncthreads();
+  return flag;
+}
 
 // Logical block index such that the blocks the hardware places on one XCD
 // (physical index b = x mod 8) form one contiguous range of logical indices.
@@ -729,7 +752,7 @@ struct CGP1Op {
   T beta;
   template <int NT>
   __device__ bool begin() {
-    if (st->done) return false;
+    if (block_read_done(st)) return false;
     const double rr = block_sum_parts<NT>(parts_in, nparts_in, nred_in, 0);
     double thresh;
     if (k == 0) {
@@ -740,11 +763,11 @@ struct CGP1Op {
         st->thresh = thresh;
       }
       if (rhs2 == 0.0) {
-        if (is_block0_thread0()) { st->done = 3; st->rr_last = rr; st->iter = 0; }
+        if (is_block0_thread0()) { st->done = 3; st->rr_last = rr; st->iter = 0; st->done_iter = 0; }
         return false;
       }
     } else {
-      thresh = st->thresh;
+      thresh = ld_dev(&st->thresh);
     }
     const bool bad = !isfinite(rr);
     if (bad || rr <= thresh) {
@@ -752,10 +775,11 @@ struct CGP1Op {
         st->done = bad ? 2 : 1;
         st->rr_last = rr;
         st->iter = k;
+        st->done_iter = k;
       }
       return false;
     }
-    beta = (k == 0) ? T(0) : (T)(rr / st->rrh[(k - 1) & 1]);
+    beta = (k == 0) ? T(0) : (T)(rr / ld_dev(&st->rrh[(k - 1) & 1]));
     if (is_block0_thread0()) {
       st->rrh[k & 1] = rr;
       st->iter = k;
@@ -829,11 +853,11 @@ struct CGP2Op {
   T alpha;
   template <int NT>
   __device__ bool begin() {
-    if (st->done) return false;
+    if (block_read_done(st)) return false;
     const double pap = block_sum_parts<NT>(parts_in, nparts_in, 1, 0);
-    const double a = st->rrh[k & 1] / pap;
+    const double a = ld_dev(&st->rrh[k & 1]) / pap;
     if (!isfinite(a) || pap <= 0.0) {
-      if (is_block0_thread0()) { st->done = 2; st->iter = k; }
+      if (is_block0_thread0()) { st->done = 2; st->iter = k; st->done_iter = k; }
       return false;
     }
     alpha = (T)a;
@@ -916,14 +940,13 @@ __global__ void __launch_bounds__(NT) k_cg_update(Geom g, CGP2Op<T> op) {
 template <int NT>
 __device__ inline double2 block_sum_parts2(const double* parts, int n) {
   __shared__ double sh[2][NT / 64];
-  const double2* pp = reinterpret_cast<const double2*>(parts);
   double s0 = 0.0, s1 = 0.0;
   for (int b0 = threadIdx.x; b0 < n; b0 += 8 * NT) {
     double2 v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int b = b0 + u * NT;
-      v[u] = b < n ? pp[b] : make_double2(0.0, 0.0);
+      v[u] = b < n ? make_double2(ld_dev(parts + 2 * b), ld_dev(parts + 2 * b + 1)) : make_double2(0.0, 0.0);
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -956,21 +979,23 @@ __device__ inline double2 block_sum_parts2(const double* parts, int n) {
 template <int NT>
 __device__ inline bool cg1r_prologue(CGState* st, const double* parts_in, int nparts_in, int k, int last, double& a,
                                      double& b) {
-  if (st->done) return false;
+  if (block_read_done(st)) return false;
   const double2 gd = block_sum_parts2<NT>(parts_in, nparts_in);
   const double gam = gd.x, del = gd.y;
-  if (!isfinite(gam) || !isfinite(del) || gam <= st->thresh || last) {
+  const double thresh = ld_dev(&st->thresh);
+  if (!isfinite(gam) || !isfinite(del) || gam <= thresh || last) {
     if (is_block0_thread0()) {
       if (!isfinite(gam) || !isfinite(del)) st->done = 2;
-      else if (gam <= st->thresh) st->done = 1;
+      else if (gam <= thresh) st->done = 1;
       st->rr_last = gam;
       st->rrh[k & 1] = gam;
       st->iter = k;
+      st->done_iter = k;
     }
     return false;
   }
-  b = k == 0 ? 0.0 : gam / st->rrh[(k - 1) & 1];
-  const double den = k == 0 ? del : del - b * gam / st->ah[(k - 1) & 1];
+  b = k == 0 ? 0.0 : gam / ld_dev(&st->rrh[(k - 1) & 1]);
+  const double den = k == 0 ? del : del - b * gam / ld_dev(&st->ah[(k - 1) & 1]);
   a = gam / den;
   if (!(den > 0.0) || !isfinite(a)) {
     // p.Ap <= 0 from finite scalars: the recurrences have drifted to rounding level
@@ -980,6 +1005,7 @@ __device__ inline bool cg1r_prologue(CGState* st, const double* parts_in, int np
       st->rr_last = gam;
       st->rrh[k & 1] = gam;
       st->iter = k;
+      st->done_iter = k;
     }
     return false;
   }
@@ -1017,7 +1043,7 @@ struct CGWInitOp {
       st->thresh = tol2 * rhs2;
     }
     if (rhs2 == 0.0) {
-      if (is_block0_thread0()) { st->done = 3; st->rr_last = 0.0; st->iter = 0; }
+      if (is_block0_thread0()) { st->done = 3; st->rr_last = 0.0; st->iter = 0; st->done_iter = 0; }
       return false;
     }
     return true;
@@ -1150,10 +1176,11 @@ struct TrialOp {
   double t;
   BoxFrame f;
   double* parts_out;
+  double a = 1.0;  // v = a u_start + t d (a = cos theta on the Lagrange method's great circle)
   template <int NT>
   __device__ bool begin() { return true; }
   __device__ void apply(long long i, int ii, int jj, int kk, double* red) const {
-    const double vi = us[i] + t * d[i];
+    const double vi = a * us[i] + t * d[i];
     v[i] = vi;
     double dx, dy, dz;
     f.rel(ii, jj, kk, dx, dy, dz);
@@ -1213,8 +1240,13 @@ struct RhsOp {
   int R, nx, ny, nz;
   BoxFrame f;
   double* parts_out;
+  double mv[kUpdRed];  // this thread's copy of the moments
   template <int NT>
-  __device__ bool begin() { return true; }
+  __device__ bool begin() {
+    if (mom)
+      for (int q = 0; q < kUpdRed; ++q) mv[q] = ld_dev(mom + q);
+    return true;
+  }
   __device__ void apply(long long i, int ii, int jj, int kk, double*) const {
     double val = v[i] * v[i] + b[i];
     if (mom && (ii < R || jj < R || kk < R || ii >= nx - R || jj >= ny - R || kk >= nz - R)) {
@@ -1223,12 +1255,12 @@ struct RhsOp {
       const double h = f.h;
       double add = 0.0;
       for (int p = 1; p <= R; ++p) {
-        if (ii - p < 0) add += W.w[p] * phi_multipole(mom, dx - p * h, dy, dz);
-        if (ii + p >= nx) add += W.w[p] * phi_multipole(mom, dx + p * h, dy, dz);
-        if (jj - p < 0) add += W.w[p] * phi_multipole(mom, dx, dy - p * h, dz);
-        if (jj + p >= ny) add += W.w[p] * phi_multipole(mom, dx, dy + p * h, dz);
-        if (kk - p < 0) add += W.w[p] * phi_multipole(mom, dx, dy, dz - p * h);
-        if (kk + p >= nz) add += W.w[p] * phi_multipole(mom, dx, dy, dz + p * h);
+        if (ii - p < 0) add += W.w[p] * phi_multipole(mv, dx - p * h, dy, dz);
+        if (ii + p >= nx) add += W.w[p] * phi_multipole(mv, dx + p * h, dy, dz);
+        if (jj - p < 0) add += W.w[p] * phi_multipole(mv, dx, dy - p * h, dz);
+        if (jj + p >= ny) add += W.w[p] * phi_multipole(mv, dx, dy + p * h, dz);
+        if (kk - p < 0) add += W.w[p] * phi_multipole(mv, dx, dy, dz - p * h);
+        if (kk + p >= nz) add += W.w[p] * phi_multipole(mv, dx, dy, dz + p * h);
       }
       val += add * (0.25 / M_PI);
     }
@@ -1289,7 +1321,7 @@ struct GradOp {
   double shift;
   template <int NT>
   __device__ bool begin() {
-    shift = -eta + (*Cptr) * inv_mu;
+    shift = -eta + ld_dev(Cptr) * inv_mu;
     return true;
   }
   __device__ double load(long long i) const { return fabs(v[i]); }
@@ -1319,6 +1351,7 @@ struct GradOp {
     red[G_XC] += eps * u2;
     red[G_ES] += (u2 + b[i]) * ph;
     red[G_U2] += u2;
+    red[G_UG] += u * g;
   }
 };
 

@@ -25,25 +25,34 @@ def _csv(path, rows):
 
 
 def test_counter_summary_scales_by_the_reference_copy(tmp_path):
-    # the copy of 256 MiB reads 131072 KiB on FETCH_SIZE (factor 2) and 262144 KiB on
-    # WRITE_SIZE (factor 1); the CG kernel's per-dispatch mean is scaled by the same factor
-    kern = "void alofdft::k_stencil2<float, 6, 4, 2, 1, alofdft::CGP1LOp<float> >(alofdft::Geom)"
+    # the copy of 256 MiB reads 131072 KiB on FETCH_SIZE (factor 2: a 128-byte read request
+    # counts as 64 bytes) and 262144 KiB on WRITE_SIZE (factor 1); the CG kernels' per-dispatch
+    # means are scaled by the same factor and summed over the two launches of an iteration
+    st = "void alofdft::k_stencil2<float, 6, 4, 2, 1, alofdft::CGP1LOp<float> >(alofdft::Geom)"
+    up = "void alofdft::k_cg_update<float, 256>(alofdft::Geom, alofdft::CGP2Op<float>)"
     fetch, write = tmp_path / "f.csv", tmp_path / "w.csv"
-    _csv(fetch, [(kern, "FETCH_SIZE", 1000.0), (kern, "FETCH_SIZE", 1200.0),
-                 ("elementwise_kernel copy", "FETCH_SIZE", 131072.0), ("tiny copy", "FETCH_SIZE", 1.0)])
-    _csv(write, [(kern, "WRITE_SIZE", 500.0), ("elementwise_kernel copy", "WRITE_SIZE", 262144.0)])
+    _csv(fetch, [(st, "FETCH_SIZE", 1000.0), (st, "FETCH_SIZE", 1200.0), (up, "FETCH_SIZE", 700.0),
+                 ("__amd_rocclr_copyBuffer", "FETCH_SIZE", 131072.0), ("tiny copyBuffer", "FETCH_SIZE", 1.0)])
+    _csv(write, [(st, "WRITE_SIZE", 500.0), (up, "WRITE_SIZE", 300.0),
+                 ("__amd_rocclr_copyBuffer", "WRITE_SIZE", 262144.0)])
     out = tmp_path / "traffic.json"
-    bench.summarize_counters(str(fetch), str(write), "cg_stencil_f32_test", path=str(out))
-    ent = json.load(open(out))["cg_stencil_f32_test"]
-    assert ent["read_bytes"] == round(1100.0 * 1024 * 2.0)
-    assert ent["write_bytes"] == round(500.0 * 1024 * 1.0)
-    assert ent["bytes_per_launch"] == ent["read_bytes"] + ent["write_bytes"]
+    bench.summarize_counters(str(fetch), str(write), "cg_f32_test", path=str(out))
+    ent = json.load(open(out))["cg_f32_test"]
+    assert ent["read_bytes"] == round((1100.0 + 700.0) * 1024 * 2.0)
+    assert ent["write_bytes"] == round((500.0 + 300.0) * 1024 * 1.0)
+    assert ent["bytes_per_iteration"] == ent["read_bytes"] + ent["write_bytes"]
     assert ent["kernels_sha256_16"] == bench.kernel_digest()
     # the gate: the bytes are reported only while the kernel sources match
-    assert bench.traffic_for("cg_stencil_f32_test", path=str(out)) == ent["bytes_per_launch"]
+    assert bench.traffic_for("cg_f32_test", path=str(out)) == ent["bytes_per_iteration"]
     data = json.load(open(out))
-    data["cg_stencil_f32_test"]["kernels_sha256_16"] = "0" * 16
+    data["cg_f32_test"]["kernels_sha256_16"] = "0" * 16
     json.dump(data, open(out, "w"))
-    assert bench.traffic_for("cg_stencil_f32_test", path=str(out)) is None
+    assert bench.traffic_for("cg_f32_test", path=str(out)) is None
     assert bench.traffic_for("absent", path=str(out)) is None
 
+
+def test_fifo_replay_and_percentiles():
+    # the sequential baseline replays the arrivals through one FIFO server
+    assert bench.fifo_latencies([0.0, 0.5, 3.0], [1.0, 1.0, 1.0]) == [1.0, 1.5, 1.0]
+    v = list(range(1, 101))
+    assert bench.pct(v, 0.5) == 50 and bench.pct(v, 0.99) == 99 and bench.pct([7.0], 0.99) == 7.0
