@@ -254,6 +254,19 @@ int alofdft_relax(alofdft_ctx* ctx, const alofdft_system* sys, const alofdft_par
 int alofdft_apply_laplacian(alofdft_ctx* ctx, const int n[3], double h, int fd_half_width, int dtype,
                             const void* x_dev, void* y_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): alofdft_apply_laplacian without any
+ * allocation.  Same arguments and result; the padded copies of x and y live in a
+ * fixed 64 MiB device array of the library (held on every device the library runs on
+ * until the process ends) instead of context workspace.  The work is enqueued on the
+ * context stream and NOT waited for: y is complete when that stream reaches this point.
+ * Every call on a device shares that device's array, so calls that overlap on one device
+ * (other contexts or streams) race; the array keeps the last call's contents (the halo
+ * is cleared by each call).  INVALID_ARGUMENT for bad sizes and for a grid whose two
+ * padded arrays need more than 64 MiB (for example beyond about 110^3 in FP64). */
+int alofdft_apply_laplacian_noalloc(alofdft_ctx* ctx, const int n[3], double h, int fd_half_width, int dtype,
+                                    const void* x_dev, void* y_dev);
+
 /* Discrete Poisson problem -(1/4pi) Delta_h phi = rho (Eq. Poisson:Discretized)
  * with boundary values `bc` (ALOFDFT_BC_*), solved by conjugate gradients in
  * `precision` (ALOFDFT_FP64 / FP32_REFINED) from the guess in phi_dev to

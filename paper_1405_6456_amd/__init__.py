@@ -114,6 +114,8 @@ def lib():
         L.alofdft_relax.argtypes = [_VP, C.POINTER(SystemS), C.POINTER(Params), C.POINTER(RelaxParams), _DP, _DP,
                                     _DP, C.POINTER(Result), C.POINTER(RelaxInfo)]
         L.alofdft_apply_laplacian.argtypes = [_VP, C.POINTER(C.c_int), C.c_double, C.c_int, C.c_int, _VP, _VP]
+        L.alofdft_apply_laplacian_noalloc.argtypes = [_VP, C.POINTER(C.c_int), C.c_double, C.c_int, C.c_int, _VP,
+                                                      _VP]
         L.alofdft_poisson.argtypes = [_VP, C.POINTER(C.c_int), C.c_double, _DP, C.c_int, C.c_int, C.c_int, _VP,
                                       _VP, C.c_double, C.c_int, C.POINTER(C.c_longlong), _DP]
         L.alofdft_energy_gradient.argtypes = [_VP, C.POINTER(SystemS), C.POINTER(Params), _VP, C.c_double,

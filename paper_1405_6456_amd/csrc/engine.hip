@@ -1710,6 +1710,41 @@ int guarded(alofdft_ctx* c, const std::function<int()>& f);
 
 }  // namespace
 
+// ----------------------------------------------------------------- allocation-free scratch
+// Scratch memory of alofdft_apply_laplacian_noalloc: the padded copies of x and y.  A
+// file-scope device array of fixed size, held by every device the library runs on until
+// the process ends.  In host code `scratch` names a host-side stand-in, never the device
+// memory: its device address is taken once per device with hipGetSymbolAddress (with that
+// device current) when a context is created there, and only that address is passed on.
+constexpr size_t kScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `dev` (the current device), resolved once per device.
+int resolve_scratch(alofdft_ctx* c, int dev) {
+  require(c, dev >= 0 && dev < kMaxDevices, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIPC(c, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    require(c, ptr != nullptr, "no device address for the scratch array");
+    g_scratch_ptr[dev] = ptr;
+  }
+  return ALOFDFT_OK;
+}
+
+void* scratch_ptr(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return dev >= 0 && dev < kMaxDevices ? g_scratch_ptr[dev] : nullptr;
+}
+
+}  // namespace
+
 // ================================================================= C ABI
 namespace {
 
@@ -2124,11 +2159,11 @@ int alofdft_create(alofdft_ctx** out, int hip_device, void* hip_stream) {
     c->trace = g_trace_file != nullptr;
     c->trace_hash = c->trace && std::getenv("ALOFDFT_TRACE_HASH") != nullptr;
   }
-  int st = guarded(c, [&]() {
+  int st = guarded(c, [&]() {  // guarded makes hip_device current
     HIPC(c, hipHostMalloc((void**)&c->pin, 4096, hipHostMallocDefault));
     HIPC(c, hipEventCreate(&c->ev0));
     HIPC(c, hipEventCreate(&c->ev1));
-    return ALOFDFT_OK;
+    return resolve_scratch(c, hip_device);
   });
   if (st != ALOFDFT_OK) {
     alofdft_destroy(c);
@@ -2263,6 +2298,46 @@ int alofdft_apply_laplacian(alofdft_ctx* c, const int n[3], double h, int fdn, i
       unpack<float, float>(c, g, py, (float*)y);
     }
     sync(c);
+    return ALOFDFT_OK;
+  });
+}
+
+int alofdft_apply_laplacian_noalloc(alofdft_ctx* c, const int n[3], double h, int fdn, int dtype, const void* x,
+                                    void* y) {
+  if (!c) return ALOFDFT_INVALID_ARGUMENT;
+  return guarded(c, [&]() {
+    require(c, n && x && y, "null argument");
+    require(c, fdn >= 1 && fdn <= kMaxRadius, "fd_half_width must be in 1..8");
+    require(c, h > 0 && std::isfinite(h), "h must be > 0");
+    require(c, dtype == 0 || dtype == 1, "dtype must be 0 (double) or 1 (float)");
+    for (int a = 0; a < 3; ++a) require(c, n[a] >= 1, "n must be >= 1");
+    const Geom g = make_geom(n, fdn);
+    const size_t es = dtype == 0 ? sizeof(double) : sizeof(float);
+    const size_t arr = ((size_t)g.total * es + 255) / 256 * 256;  // one padded array, 256-byte aligned
+    if (2 * arr > kScratchBytes) {
+      set_err(c, "grid needs %zu bytes of scratch for its padded x and y; the allocation-free Laplacian has %zu",
+              2 * arr, kScratchBytes);
+      throw Fail{ALOFDFT_INVALID_ARGUMENT};
+    }
+    unsigned char* base = (unsigned char*)scratch_ptr(c->device);
+    require(c, base != nullptr, "scratch not resolved on this device");
+    if (dtype == 0) {
+      double* px = (double*)base;
+      double* py = (double*)(base + arr);
+      fill<double>(c, px, g.total, 0.0);  // the zero halo of this geometry
+      pack<double, double>(c, g, (const double*)x, px);
+      LapOp<double> op{px, py, nullptr};
+      launch_stencil(c, g, stencil_weights<double>(fdn, h, 1.0), op);
+      unpack<double, double>(c, g, py, (double*)y);
+    } else {
+      float* px = (float*)base;
+      float* py = (float*)(base + arr);
+      fill<float>(c, px, g.total, 0.0f);
+      pack<float, float>(c, g, (const float*)x, px);
+      LapOp<float> op{px, py, nullptr};
+      launch_stencil(c, g, stencil_weights<float>(fdn, h, 1.0), op);
+      unpack<float, float>(c, g, py, (float*)y);
+    }
     return ALOFDFT_OK;
   });
 }
