@@ -151,3 +151,38 @@ def test_fcc5_solution_is_the_oracle_minimiser(C, orc, precision, schedule):
     assert abs(e["E_total"] - out["E_total"]) / S.M < 1e-9
     f_o = orc.forces(S, prm, phi_o)
     assert np.abs(f_o - out["forces"]).max() < 1e-6
+
+
+@pytest.mark.timeout(900)
+def test_fcc10_fp32_refined_solution_is_the_oracle_minimiser(orc, capsys):
+    # 4000 atoms, 185^3 nodes, FP32 stencil and CG inside FP64 refinement, from the
+    # library's atomic-density guess: the same check as for fcc5 (the oracle's Euler-Lagrange
+    # residual, energy and forces at the GPU's u* and eta*).  The solve takes minutes; the
+    # library's own progress lines (one per 100 NLCG steps and per AL step) go to stderr.
+    import os
+
+    import paper_1405_6456_amd as lib
+
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    S = synth.config("fcc10")
+    os.environ["ALOFDFT_PROGRESS"] = "1"
+    try:
+        c = lib.Context(0)
+    finally:
+        del os.environ["ALOFDFT_PROGRESS"]
+    try:
+        with capsys.disabled():
+            out = c.solve(S, lib.default_params(precision=lib.FP32_REFINED, initial_guess=lib.GUESS_ATOMIC), None)
+    finally:
+        c.close()
+    assert out["status"] == 0
+    assert abs(out["C_h"]) / S.N < 1e-8
+    prm = orc.params()
+    g, e, phi_o, _ = orc.evaluate(S, prm, out["u"], eta=out["eta_star"], mu=0.0, phi=out["phi"])
+    gnorm = float(np.sqrt(S.grid.h ** 3 * np.sum(g * g)))
+    assert gnorm < 1e-5
+    assert abs(e["E_total"] - out["E_total"]) / S.M < 1e-9
+    f_o = orc.forces(S, prm, phi_o)
+    assert np.abs(f_o - out["forces"]).max() < 1e-6
