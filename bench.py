@@ -415,6 +415,10 @@ def serve(args):
                     if r is not None:
                         results[k] = r
                         pending.discard(k)
+                        done = len(reqs) - len(pending)
+                        if done % 16 == 0:
+                            print(f"serve f={f}: {done}/{len(reqs)} completed at {time.perf_counter() - t0:.1f} s",
+                                  file=sys.stderr, flush=True)
             time.sleep(0.005)
         th.join()
         wall = time.perf_counter() - t0

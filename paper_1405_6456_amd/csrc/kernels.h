@@ -48,6 +48,15 @@ struct late_begin : std::false_type {};
 template <class Op>
 struct late_begin<Op, std::void_t<decltype(Op::LATE_BEGIN)>> : std::bool_constant<Op::LATE_BEGIN> {};
 
+// Node operands an op's epilogue reads at the node itself (NPRE of them): the streaming
+// kernel loads them one plane ahead through op.prefetch and hands them to op.storep, so
+// the wait for them does not also wait for that step's plane prefetches.  Ops without
+// NPRE read nothing at the node (or do it inside storeb).
+template <class Op, class = void>
+struct op_npre : std::integral_constant<int, 0> {};
+template <class Op>
+struct op_npre<Op, std::void_t<decltype(Op::NPRE)>> : std::integral_constant<int, Op::NPRE> {};
+
 // Reduces acc[0..NRED) over the block; thread r < NRED writes component r to out[r].
 template <int NRED, int NT>
 __device__ inline void block_reduce_store(const double* acc, double* out) {
@@ -300,10 +309,10 @@ __device__ inline void bst<double>(double* p, uint32_t nb, uint32_t vo, uint32_t
 // the lane term is per thread.  The z column of each own node streams through a
 // register queue of K = 2R+1+PD slots (PD planes prefetched ahead); the 2R halo
 // rows of the tile are loaded one row per wave instruction and the 2R*BY*VY x-halo
-// nodes by the first threads, all staged in LDS (double buffered, one barrier per
-// plane).  With alt set, odd z chunks are swept downwards, so the planes two
+// nodes by the first threads, HS planes ahead in HS register sets, all staged in LDS
+// (double buffered, one barrier per plane).  With alt set, odd z chunks are swept downwards, so the planes two
 // neighbouring chunks share are read by both at about the same time.
-template <typename T, int R, int BY, int VY, int PD, class Op>
+template <typename T, int R, int BY, int VY, int PD, class Op, int HS = 1>
 __global__ void __launch_bounds__(64 * BY) k_stencil2(Geom g, StencilW<T> W, int zc, int tiles_x, int tiles_y,
                                                       int alt, Op op) {
   constexpr int BX = 64;
@@ -318,6 +327,7 @@ __global__ void __launch_bounds__(64 * BY) k_stencil2(Geom g, StencilW<T> W, int
   constexpr int NRED = Op::NRED;
   constexpr uint32_t ES = sizeof(T);
   static_assert(K % 2 == 0, "queue length must be even (LDS parity)");
+  static_assert(K % HS == 0, "halo register sets must divide the queue");
   __shared__ T lds[2][LY * LX];
 
   Op o = op;
@@ -330,15 +340,18 @@ __global__ void __launch_bounds__(64 * BY) k_stencil2(Geom g, StencilW<T> W, int
 
   const uint32_t nb = (uint32_t)(g.total * (long long)ES);
   const int ntile = tiles_x * tiles_y;
-  // chunk-fastest order within each XCD's contiguous range: the chunks of one tile
-  // column run together (their shared z planes meet in L2), and an XCD owns whole
-  // tile columns
   const int nchunks = gridDim.x / ntile;
   const int lb = xcd_swizzle(blockIdx.x, gridDim.x);
-  const int tile = lb / nchunks, chunk = lb % nchunks;
+  // mode bit 1 clear: chunk-fastest order within each XCD's contiguous range, so an XCD
+  // owns whole tile columns and the chunks of one column meet in its L2; set:
+  // tile-fastest, so an XCD owns whole chunks (a z slab when the chunk count is a
+  // multiple of 8) and the x-y halos of neighbouring tiles meet in its L2.
+  // Bit 0: odd chunks sweep downwards.
+  const bool slab = (alt & 2) != 0;
+  const int tile = slab ? lb % ntile : lb / nchunks, chunk = slab ? lb / ntile : lb % nchunks;
   const int x0 = (tile % tiles_x) * BX, y0 = (tile / tiles_x) * TY;
   const int zbeg = chunk * zc, zend = min(zbeg + zc, g.nz), len = zend - zbeg;
-  const bool down = alt && (chunk & 1);
+  const bool down = (alt & 1) && (chunk & 1);
   const int zfirst = down ? zend - 1 : zbeg;
   const long long pstep = down ? -g.plane : g.plane;
   const int lane = threadIdx.x & 63;
@@ -379,87 +392,109 @@ __global__ void __launch_bounds__(64 * BY) k_stencil2(Geom g, StencilW<T> W, int
   const uint32_t xbias = (uint32_t)R * ES;         // x halo: offsets carry +R columns
 
   T q[K][VY];
-  T hrg[HR];
-  T xrg[XH];
+  T hrg[HS][HR];
+  T xrg[HS][XH];
+  constexpr int NPRE = op_npre<Op>::value;
+  T pre[2][VY][NPRE > 0 ? NPRE : 1];  // node operands of the epilogue, plane t in set t & 1
   double red[NRED > 0 ? NRED : 1];
 #pragma unroll
   for (int r = 0; r < (NRED > 0 ? NRED : 1); ++r) red[r] = 0.0;
+
+  // Every global load and store of the streaming loop is issued unconditionally (planes
+  // past the chunk are clamped to its last plane and their values never used; lanes
+  // outside the interior store zeros into the zero padding), so the number of memory
+  // operations in flight is the same on every path and the waits for a prefetched
+  // plane do not also wait for the loads issued after it.
+  constexpr bool HALL = (2 * R) % BY == 0;  // every wave loads all its HR halo rows
+  const int tlast = len - 1;
 
   // queue: logical planes -R .. R+PD-1 into slots 0 .. K-2 (slot of plane t+d at
   // unrolled step s is (s + R + d) mod K); the last slot is filled by the first prefetch
 #pragma unroll
   for (int m = 0; m < K - 1; ++m) {
-    const int t = m - R;
-    if (t <= len - 1 + R) {
-      const uint32_t so = plane_off(t) + own_row;
+    const uint32_t so = plane_off(min(m - R, tlast + R)) + own_row;
 #pragma unroll
-      for (int v = 0; v < VY; ++v) q[m][v] = o.loadb(nb, vl, so + v * rowb);
-    } else {
-#pragma unroll
-      for (int v = 0; v < VY; ++v) q[m][v] = T(0);
-    }
+    for (int v = 0; v < VY; ++v) q[m][v] = o.loadb(nb, vl, so + v * rowb);
   }
 #pragma unroll
   for (int v = 0; v < VY; ++v) q[K - 1][v] = T(0);
-  {
-    const uint32_t so = plane_off(0);
+  // x-y halo of planes 0 .. HS-1 into sets 0 .. HS-1 (plane t is staged from set t mod HS)
+  auto load_halo = [&](int t, int set) __attribute__((always_inline)) {
+    const uint32_t so = plane_off(min(t, tlast));
 #pragma unroll
-    for (int i = 0; i < HR; ++i) hrg[i] = hok[i] ? o.loadb(nb, vl, so + hro[i] - rbias) : T(0);
+    for (int i = 0; i < HR; ++i)
+      if (HALL || hok[i]) hrg[set][i] = o.loadb(nb, vl, so + hro[i] - rbias);
 #pragma unroll
-    for (int m = 0; m < XH; ++m) xrg[m] = xok[m] ? o.loadb(nb, xo[m], so - xbias) : T(0);
-  }
+    for (int m = 0; m < XH; ++m) xrg[set][m] = o.loadb(nb, xok[m] ? xo[m] : 0u, so - xbias);
+  };
+#pragma unroll
+  for (int d = 0; d < HS; ++d) load_halo(d, d);
+  auto load_pre = [&](int t, int set) __attribute__((always_inline)) {
+    if constexpr (NPRE > 0) {
+      const uint32_t so = plane_off(min(t, tlast)) + own_row;
+#pragma unroll
+      for (int v = 0; v < VY; ++v) o.prefetch(nb, vl, so + v * rowb, pre[set][v]);
+    }
+  };
+  load_pre(0, 0);
   if constexpr (LATE) {
     if (!o.template begin<NT>()) return;
   }
 
-  for (int t0 = 0; t0 < len; t0 += K) {
+  auto step = [&](int s, int t) __attribute__((always_inline)) {
+    T* L = lds[s & 1];
+    const int hs = s % HS;
 #pragma unroll
-    for (int s = 0; s < K; ++s) {
-      const int t = t0 + s;
-      if (t < len) {
-        T* L = lds[s & 1];
+    for (int v = 0; v < VY; ++v) L[(R + wv * VY + v) * LX + R + lane] = q[(s + R) % K][v];
 #pragma unroll
-        for (int v = 0; v < VY; ++v) L[(R + wv * VY + v) * LX + R + lane] = q[(s + R) % K][v];
+    for (int i = 0; i < HR; ++i)
+      if (HALL || hok[i]) L[hly[i] * LX + R + lane] = hrg[hs][i];
 #pragma unroll
-        for (int i = 0; i < HR; ++i)
-          if (hok[i]) L[hly[i] * LX + R + lane] = hrg[i];
+    for (int m = 0; m < XH; ++m)
+      if (xok[m]) L[xl[m]] = xrg[hs][m];
+    load_pre(t + 1, (s + 1) & 1);
+    {
+      const uint32_t so = plane_off(min(t + R + PD, tlast + R)) + own_row;
 #pragma unroll
-        for (int m = 0; m < XH; ++m)
-          if (xok[m]) L[xl[m]] = xrg[m];
-        if (t + PD <= len - 1) {
-          const uint32_t so = plane_off(t + R + PD) + own_row;
-#pragma unroll
-          for (int v = 0; v < VY; ++v) q[(s + 2 * R + PD) % K][v] = o.loadb(nb, vl, so + v * rowb);
-        }
-        if (t + 1 < len) {
-          const uint32_t so = plane_off(t + 1);
-#pragma unroll
-          for (int i = 0; i < HR; ++i)
-            if (hok[i]) hrg[i] = o.loadb(nb, vl, so + hro[i] - rbias);
-#pragma unroll
-          for (int m = 0; m < XH; ++m)
-            if (xok[m]) xrg[m] = o.loadb(nb, xo[m], so - xbias);
-        }
-        __syncthreads();
-        const uint32_t so = plane_off(t) + own_row;
-        const int z = zfirst + (down ? -t : t);
-#pragma unroll
-        for (int v = 0; v < VY; ++v) {
-          const T* row = L + (R + wv * VY + v) * LX + R + lane;
-          const T c = q[(s + R) % K][v];
-          T acc = W.c0 * c;
-#pragma unroll
-          for (int p = 1; p <= R; ++p) {
-            const int a = v - p, b = v + p;  // own-row index of the y neighbours
-            const T ya = (a >= 0) ? q[(s + R) % K][a >= 0 ? a : 0] : row[-p * LX];
-            const T yb = (b < VY) ? q[(s + R) % K][b < VY ? b : 0] : row[p * LX];
-            acc += W.w[p] * (((q[(s + R - p) % K][v] + q[(s + R + p) % K][v]) + (row[-p] + row[p])) + (ya + yb));
-          }
-          const int gx = x0 + lane, gy = y0 + wv * VY + v;
-          if (gy < g.ny && gx < g.nx) o.storeb(nb, vl, so + v * rowb, gx, gy, z, c, acc, red);
-        }
-      }
+      for (int v = 0; v < VY; ++v) q[(s + 2 * R + PD) % K][v] = o.loadb(nb, vl, so + v * rowb);
     }
+    load_halo(t + HS, hs);
+    __syncthreads();
+    const uint32_t so = plane_off(t) + own_row;
+    const int z = zfirst + (down ? -t : t);
+#pragma unroll
+    for (int v = 0; v < VY; ++v) {
+      const T* row = L + (R + wv * VY + v) * LX + R + lane;
+      const T c = q[(s + R) % K][v];
+      T acc = W.c0 * c;
+#pragma unroll
+      for (int p = 1; p <= R; ++p) {
+        const int a = v - p, b = v + p;  // own-row index of the y neighbours
+        const T ya = (a >= 0) ? q[(s + R) % K][a >= 0 ? a : 0] : row[-p * LX];
+        const T yb = (b < VY) ? q[(s + R) % K][b < VY ? b : 0] : row[p * LX];
+        acc += W.w[p] * (((q[(s + R - p) % K][v] + q[(s + R + p) % K][v]) + (row[-p] + row[p])) + (ya + yb));
+      }
+      const int gx = x0 + lane, gy = y0 + wv * VY + v;
+      // a lane outside the interior sits in the zero padding, where every input of the
+      // op is zero: with the stencil value zeroed too, the op stores zeros there and
+      // adds nothing to its sums
+      const bool in = gy < g.ny && gx < g.nx;
+      if constexpr (NPRE > 0)
+        o.storep(nb, vl, so + v * rowb, c, in ? acc : T(0), pre[s & 1][v], red);
+      else
+        o.storeb(nb, vl, so + v * rowb, gx, gy, z, c, in ? acc : T(0), red);
+    }
+  };
+
+  int t0 = 0;
+  for (; t0 + K <= len; t0 += K) {
+#pragma unroll
+    for (int s = 0; s < K; ++s) step(s, t0 + s);
+  }
+  if (t0 < len) {
+#pragma unroll
+    for (int s = 0; s < K; ++s)
+      if (t0 + s < len) step(s, t0 + s);
   }
   if constexpr (NRED > 0) {
     block_reduce_store<NRED, NT>(red, o.parts_out + (long long)blockIdx.x * NRED);
@@ -496,15 +531,18 @@ __global__ void __launch_bounds__(64 * BY) k_stencil3(Geom g, StencilW<T> W, int
 
   const uint32_t nb = (uint32_t)(g.total * (long long)ES);
   const int ntile = tiles_x * tiles_y;
-  // chunk-fastest order within each XCD's contiguous range: the chunks of one tile
-  // column run together (their shared z planes meet in L2), and an XCD owns whole
-  // tile columns
   const int nchunks = gridDim.x / ntile;
   const int lb = xcd_swizzle(blockIdx.x, gridDim.x);
-  const int tile = lb / nchunks, chunk = lb % nchunks;
+  // mode bit 1 clear: chunk-fastest order within each XCD's contiguous range, so an XCD
+  // owns whole tile columns and the chunks of one column meet in its L2; set:
+  // tile-fastest, so an XCD owns whole chunks (a z slab when the chunk count is a
+  // multiple of 8) and the x-y halos of neighbouring tiles meet in its L2.
+  // Bit 0: odd chunks sweep downwards.
+  const bool slab = (alt & 2) != 0;
+  const int tile = slab ? lb % ntile : lb / nchunks, chunk = slab ? lb / ntile : lb % nchunks;
   const int x0 = (tile % tiles_x) * BX, y0 = (tile / tiles_x) * TY;
   const int zbeg = chunk * zc, zend = min(zbeg + zc, g.nz), len = zend - zbeg;
-  const bool down = alt && (chunk & 1);
+  const bool down = (alt & 1) && (chunk & 1);
   const int zfirst = down ? zend - 1 : zbeg;
   const long long pstep = down ? -g.plane : g.plane;
   const int lane = threadIdx.x & 63;
@@ -832,6 +870,20 @@ struct CGP1LOp : CGP1Op<T> {
       pn = c + beta * bld((const T*)pnew, nb, vo, so);
       apn = ar + beta * bld((const T*)Ap, nb, vo, so);
     }
+    bst(pnew, nb, vo, so, pn);
+    bst(Ap, nb, vo, so, apn);
+    red[0] += (double)pn * (double)apn;
+  }
+  // the same update with p_old and (A p)_old loaded a plane ahead (iteration 0 has no
+  // p_old: beta = 0 and the loaded values, whatever they hold, are not used)
+  static constexpr int NPRE = 2;
+  __device__ void prefetch(uint32_t nb, uint32_t vo, uint32_t so, T* pre) const {
+    pre[0] = bld((const T*)pnew, nb, vo, so);
+    pre[1] = bld((const T*)Ap, nb, vo, so);
+  }
+  __device__ void storep(uint32_t nb, uint32_t vo, uint32_t so, T c, T ar, const T* pre, double* red) const {
+    const T pn = k == 0 ? c : c + beta * pre[0];
+    const T apn = k == 0 ? ar : ar + beta * pre[1];
     bst(pnew, nb, vo, so, pn);
     bst(Ap, nb, vo, so, apn);
     red[0] += (double)pn * (double)apn;
