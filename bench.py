@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--rate-factors", default="0.5,1,2",
                     help="serve: arrival rates as multiples of the sequential FP64 service rate")
     ap.add_argument("--slots", type=int, default=4, help="serve: concurrent request slots")
+    ap.add_argument("--slot-blocks", default="256",
+                    help="serve: workgroups per stencil launch of each slot (the server default 256; 0: one round), comma list")
     return ap.parse_args()
 
 
@@ -389,11 +391,12 @@ def serve(args):
         svc64[m] = time.perf_counter() - t
     service = [svc64[m] for m in ms]
     c_seq = 1.0 / (sum(service) / len(service))
-    for f in [float(x) for x in args.rate_factors.split(",")]:
+    for f, sb in [(float(x), int(y)) for x in args.rate_factors.split(",") for y in args.slot_blocks.split(",")]:
         rate = f * c_seq
         arrivals = synth.arrival_times(len(reqs), rate)
         seq_lat = fifo_latencies(list(arrivals), service)
         srv = lib.Server(0, max_slots=args.slots)
+        srv.set_tuning(sb)
         tickets = [None] * len(reqs)
         t0 = time.perf_counter()
 
@@ -424,14 +427,15 @@ def serve(args):
         wall = time.perf_counter() - t0
         st = srv.stats()
         srv.close()
-        print(f"serve f={f}: {st['completed']} done in {wall:.1f} s", file=sys.stderr, flush=True)
+        print(f"serve f={f} slot blocks {sb}: {st['completed']} done in {wall:.1f} s", file=sys.stderr, flush=True)
         err_e = max(abs(results[k]["E_total"] - ref[m]["E_total"]) / reqs[k].M for m, k in first.items())
         err_f = max(float(np.abs(results[k]["forces"] - ref[m]["forces"]).max()) for m, k in first.items())
         print(json.dumps({
             "metric": METRIC, "mode": "serve", "value": round(st["solves_per_s"], 4), "unit": "solves/s",
             "n_gpus": 1, "higher_is_better": True, "dtype": "f32 stencil/CG + f64 refinement", "data": "synthetic",
             "config": {"workload": f"serving stream: {len(reqs)} fcc m^3 clusters, m in {{1,2,3}} (48^3..79^3 nodes),"
-                                   f" Poisson arrivals at {f} x the sequential FP64 rate", "slots": args.slots},
+                                   f" Poisson arrivals at {f} x the sequential FP64 rate", "slots": args.slots,
+                       "slot_blocks": sb},
             "served": {"p50_ms": round(st["p50_ms"], 1), "p99_ms": round(st["p99_ms"], 1),
                        "mean_ms": round(st["mean_ms"], 1), "solves_per_s": round(st["solves_per_s"], 4),
                        "wall_s": round(wall, 1), "completed": st["completed"],

@@ -436,6 +436,17 @@ int alofdft_server_get_stats(alofdft_server* srv, alofdft_server_stats* st);
  * request that has finished keeps its result.  INVALID_ARGUMENT for an unknown ticket. */
 int alofdft_server_cancel(alofdft_server* srv, uint64_t ticket);
 
+/* Workgroups per stencil launch of every slot (alofdft_set_tuning's target_blocks; 0 is
+ * one round of resident workgroups).  Default ALOFDFT_SERVER_SLOT_BLOCKS: launches smaller
+ * than a round leave the device room to run the slots' kernels side by side (measured on
+ * the fcc1-3 stream with 4 slots at twice the sequential FP64 capacity: 0.93 solves/s and
+ * p50/p99 7.0/15.1 s against 0.86 and 10.6/20.2 s at one round).  The shape of a launch
+ * changes the order of its partial sums, so results depend on it (within the solver's
+ * tolerance) but never on the other requests: a served result equals a context's solve with
+ * the same target_blocks.  INVALID_ARGUMENT while any request is queued or running. */
+#define ALOFDFT_SERVER_SLOT_BLOCKS 256
+int alofdft_server_set_tuning(alofdft_server* srv, int target_blocks);
+
 /* Stops the server: queued requests are cancelled, running ones stop at their next
  * check, then the workers exit and every slot's device memory is freed. */
 void alofdft_server_destroy(alofdft_server* srv);

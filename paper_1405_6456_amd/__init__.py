@@ -21,6 +21,7 @@ AL, PENALTY, LAGRANGE = 0, 1, 2
 PSEUDO_GAUSSIAN, PSEUDO_FD_LAPLACIAN = 0, 1
 GUESS_UNIFORM, GUESS_ATOMIC = 0, 1
 STOP_CONSTRAINT, STOP_ENERGY_CHANGE = 0, 1
+SERVER_SLOT_BLOCKS = 256  # ALOFDFT_SERVER_SLOT_BLOCKS: default workgroups per stencil launch of a server slot
 BC_ZERO, BC_MULTIPOLE = 0, 1
 FP64, FP32_REFINED = 0, 1
 
@@ -131,6 +132,7 @@ def lib():
         L.alofdft_server_poll.argtypes = [_VP, C.c_uint64, C.POINTER(Result), _DP, _DP]
         L.alofdft_server_get_stats.argtypes = [_VP, C.POINTER(ServerStats)]
         L.alofdft_server_cancel.argtypes = [_VP, C.c_uint64]
+        L.alofdft_server_set_tuning.argtypes = [_VP, C.c_int]
         L.alofdft_cancel.argtypes = [_VP]
         L.alofdft_server_destroy.argtypes = [_VP]
         L.alofdft_server_destroy.restype = None
@@ -454,6 +456,12 @@ class Server:
     def cancel(self, ticket):
         """Cancel a queued or running request (poll then reports status CANCELLED)."""
         st = lib().alofdft_server_cancel(self.handle, ticket)
+        if st != OK:
+            raise AlofdftError(st, lib().alofdft_strerror(st).decode())
+
+    def set_tuning(self, target_blocks):
+        """Workgroups per stencil launch of every slot (0: one round); only while idle."""
+        st = lib().alofdft_server_set_tuning(self.handle, int(target_blocks))
         if st != OK:
             raise AlofdftError(st, lib().alofdft_strerror(st).decode())
 

@@ -2521,6 +2521,7 @@ int alofdft_server_create(alofdft_server** out, int hip_device, size_t hbm_budge
       alofdft_server_destroy(s);
       return rc;
     }
+    c->target_blocks = ALOFDFT_SERVER_SLOT_BLOCKS;  // room for the other slots' kernels
     s->ctx.push_back(c);
     s->held.push_back(0);
     s->current.push_back(nullptr);
@@ -2636,6 +2637,15 @@ int alofdft_server_cancel(alofdft_server* s, uint64_t ticket) {
   } else {
     s->ctx[r.slot]->cancel.store(1);  // the slot's solve stops at its next check
   }
+  return ALOFDFT_OK;
+}
+
+int alofdft_server_set_tuning(alofdft_server* s, int target_blocks) {
+  if (!s || target_blocks < 0) return ALOFDFT_INVALID_ARGUMENT;
+  std::lock_guard<std::mutex> lk(s->mu);
+  // a slot's context is read by its worker only while it runs a request
+  if (s->running > 0 || !s->queue.empty()) return ALOFDFT_INVALID_ARGUMENT;
+  for (alofdft_ctx* c : s->ctx) c->target_blocks = target_blocks;
   return ALOFDFT_OK;
 }
 

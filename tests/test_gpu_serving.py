@@ -28,6 +28,7 @@ def alone():
     import paper_1405_6456_amd as lib
 
     c = ctx()
+    c.set_tuning(target_blocks=lib.SERVER_SLOT_BLOCKS)  # the launch size of a server slot
     prm = lib.default_params(precision=lib.FP32_REFINED)
     res = [c.solve(S, prm, None) for S in requests()]
     c.close()
@@ -63,6 +64,7 @@ def test_fp64_requests_same_alone_and_in_the_mix():
     import paper_1405_6456_amd as lib
 
     c = ctx()
+    c.set_tuning(target_blocks=lib.SERVER_SLOT_BLOCKS)
     prm = lib.default_params(precision=lib.FP64)
     reqs = requests()
     single = [c.solve(S, prm, None) for S in reqs]
@@ -88,6 +90,7 @@ def test_cluster_requests_same_alone_and_in_the_mix():
     reqs = [synth.fcc_cluster(m, seed=10000 + m, name=f"fcc{m}") for m in (1, 2, 3)]
     prm = lib.default_params(precision=lib.FP32_REFINED, initial_guess=lib.GUESS_ATOMIC)
     c = ctx()
+    c.set_tuning(target_blocks=lib.SERVER_SLOT_BLOCKS)
     single = [c.solve(S, prm, None) for S in reqs]
     c.close()
     srv = lib.Server(0, max_slots=4)
@@ -101,6 +104,36 @@ def test_cluster_requests_same_alone_and_in_the_mix():
         assert np.abs(r["forces"] - a["forces"]).max() <= 1e-10
         assert np.abs(r["u"] - a["u"]).max() <= 1e-10 * np.abs(a["u"]).max()
     srv.close()
+
+
+def test_slot_launch_size_keeps_results_independent_of_the_mix():
+    # with smaller stencil launches per slot (so the slots' kernels can share the device),
+    # every served result still equals a standalone context with the same launch size; the
+    # setting is refused while requests are queued or running
+    import paper_1405_6456_amd as lib
+
+    reqs = [synth.fcc_cluster(m, seed=10000 + m, name=f"fcc{m}") for m in (1, 2)]
+    prm = lib.default_params(precision=lib.FP32_REFINED, initial_guess=lib.GUESS_ATOMIC)
+    c = ctx()
+    c.set_tuning(target_blocks=128)
+    single = [c.solve(S, prm, None) for S in reqs]
+    c.close()
+    srv = lib.Server(0, max_slots=4)
+    try:
+        srv.set_tuning(128)
+        tickets = [(i, srv.submit(S, prm)) for _ in range(2) for i, S in enumerate(reqs)]
+        with pytest.raises(lib.AlofdftError):
+            srv.set_tuning(0)
+        for i, t in tickets:
+            r = srv.wait(t)
+            a = single[i]
+            assert r["status"] == 0 and a["status"] == 0
+            assert r["cg_iters"] == a["cg_iters"], (i, r["cg_iters"], a["cg_iters"])
+            assert abs(r["E_total"] - a["E_total"]) <= 1e-10 * max(1.0, abs(a["E_total"]))
+            assert np.abs(r["forces"] - a["forces"]).max() <= 1e-10
+            assert np.abs(r["u"] - a["u"]).max() <= 1e-10 * np.abs(a["u"]).max()
+    finally:
+        srv.close()
 
 
 def test_tight_budget_admits_every_request():
