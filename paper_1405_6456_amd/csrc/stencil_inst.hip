@@ -152,8 +152,16 @@ hipError_t launch_stencil_r(const LaunchCfg& lc, const Geom& g, const StencilW<T
       }
     }
     // automatic: the pipelined iteration over 64x16 tiles of 8 waves (measured 3-4 %
-    // faster at 63^3, 1 % at 109^3), the first half of schedule 1 over 64x8 tiles
+    // faster at 63^3, 1 % at 109^3); the first half of schedule 1 over 64x8 tiles of 8 waves
+    // of one row each (FP32 at 185^3: 31.2 us against 34.1 us for 4 waves of two rows, 11.6
+    // against 12.7 at 109^3), FP64 on large grids over 64x16 tiles of 8 waves (56.7 against
+    // 61.5 us at 185^3)
     if constexpr (is_cg_pipe<Op>::value) return launch_cfg2<T, R, 8, 2, 1, Op>(lc, g, W, op, nblocks, alt);
+    if constexpr (std::is_same_v<Op, CGP1LOp<double>>) {
+      if ((long long)g.nx * g.ny * g.nz > 2000000ll) return launch_cfg2<T, R, 8, 2, 1, Op>(lc, g, W, op, nblocks, alt);
+    }
+    if constexpr (std::is_same_v<Op, CGP1LOp<float>> || std::is_same_v<Op, CGP1LOp<double>>)
+      return launch_cfg2<T, R, 8, 1, 1, Op>(lc, g, W, op, nblocks, alt);
     return launch_cfg2<T, R, 4, 2, 1, Op>(lc, g, W, op, nblocks, alt);
   } else {
     return launch_stencil_plain<R, T, Op>(lc, g, W, op, nblocks);
