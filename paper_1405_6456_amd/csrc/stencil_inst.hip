@@ -196,11 +196,20 @@ hipError_t launch_stencil_plain(const LaunchCfg& lc, const Geom& g, const Stenci
           default: break;
         }
       }
-      // automatic: 64 x 8 tiles; the plain FP64 Laplacian of large grids streams
-      // faster with forward accumulation over 64 x 16 tiles, two planes ahead
+      // automatic: 64 x 8 tiles of 4 waves; the plain Laplacian of large grids with more
+      // waves per tile (measured, unconditional plane loop): FP64 64 x 16 tiles of 16 waves
+      // up to 250^3 (185^3: 34.2-36.5 us against 38-39 for forward accumulation), forward
+      // accumulation over 64 x 16 tiles above (equal to the best streaming shape at 300^3
+      // and 474^3); FP32 from 250^3 on 64 x 32 tiles of 16 waves of two rows (300^3: 82
+      // against 91 us; 474^3: 294 against 331; at 185^3 no shape beat 64 x 8 beyond the
+      // run-to-run spread)
+      const long long n3 = (long long)g.nx * g.ny * g.nz;
       if constexpr (std::is_same_v<Op, LapOp<double>>) {
-        if ((long long)g.nx * g.ny * g.nz >= 150ll * 150 * 150)
-          return launch_cfg3<T, R, 4, 4, 2, Op>(lc, g, W, op, nblocks, alt);
+        if (n3 >= 250ll * 250 * 250) return launch_cfg3<T, R, 4, 4, 2, Op>(lc, g, W, op, nblocks, alt);
+        if (n3 >= 150ll * 150 * 150) return launch_cfg2<T, R, 16, 1, 1, Op>(lc, g, W, op, nblocks, alt);
+      }
+      if constexpr (std::is_same_v<Op, LapOp<float>>) {
+        if (n3 >= 250ll * 250 * 250) return launch_cfg2<T, R, 16, 2, 1, Op>(lc, g, W, op, nblocks, alt);
       }
       return launch_cfg2<T, R, 4, 2, 1, Op>(lc, g, W, op, nblocks, alt);
     }
