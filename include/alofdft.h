@@ -316,26 +316,26 @@ int alofdft_bench_stencil(alofdft_ctx* ctx, const int n[3], int fd_half_width, i
 /* Launch tuning of a context.  stencil_variant selects the schedule of the
  * stencil passes (the residual pass of the energy gradient always uses the
  * register-addressed 64x4 kernel):
- *   -1  automatic: buffer-addressed streaming kernel over 64x8 tiles (two rows per
- *       thread, z column one plane ahead); the plain FP64 Laplacian of grids with
- *       at least 150^3 nodes uses the forward-accumulating kernel over 64x16 tiles,
- *       two planes ahead; radii other than 6 always use the first.
+ *   -1  automatic, by op, precision and grid (all measured on MI355X): the plain
+ *       Laplacian over (waves, rows per wave, planes ahead) = (4,2,1) below 150^3
+ *       nodes; FP64 (16,1,1) from 150^3 and the forward-accumulating kernel (4,4,2)
+ *       from 250^3; FP32 (16,2,1) from 250^3.  The CG first half (schedule 1)
+ *       (8,1,1); the pipelined iteration (8,2,1).  Radii other than 6 take the same
+ *       shapes.
  *   0..4  register-addressed kernels (order 12): 0: 64x8 nodes, two rows per
  *       thread, one plane ahead; 1: 64x4, one row, three ahead; 2: 64x8, one row,
  *       one ahead; 3: 64x8, one row, three ahead; 4: 64x4, one row, one ahead.
- *   5..10  buffer-addressed streaming kernel (order 12), (waves, rows per thread,
- *       planes ahead): 5 (4,2,1), 6 (4,4,1), 7 (4,2,3), 8 (4,4,3), 9 (8,2,1),
- *       10 (2,8,1).
+ *   5..10, 17..19  buffer-addressed streaming kernel (order 12), (waves, rows per
+ *       wave, planes ahead): 5 (4,2,1), 6 (4,4,1), 7 (4,2,3), 8 (4,4,3), 9 (8,2,1),
+ *       10 (2,8,1), 17 (8,1,1), 18 (16,1,1), 19 (16,2,1).
  *   11..16  forward-accumulating kernel (order 12): 11 (4,2,1), 12 (4,4,1),
  *       13 (4,2,2), 14 (8,2,1), 15 (4,4,2), 16 (8,4,1).
- *   100 + v  variant v with every z chunk swept upwards (v in 5..17; by default
+ *   100 + v  variant v with every z chunk swept upwards (v in 5..19; by default
  *       odd chunks are swept downwards).
- *   17  CG kernels only: streaming kernel (8,1,1); other passes take their
- *       automatic shape.
  * The stencil launches of the CG iterations (schedules 1 and 2 of
- * alofdft_set_cg_schedule) take variants 5, 6, 7, 9, 10, 11..16 and 17 as above;
- * every other value selects their automatic shape, (8,2,1) for the pipelined
- * iteration and (4,2,1) for schedule 1.
+ * alofdft_set_cg_schedule) take variants 5, 6, 7, 9, 10, 17, 18, 19 as above and
+ * 11..16 as the forward-accumulating (4,2,1); every other value selects their
+ * automatic shape.
  * target_blocks is the number of stencil workgroups to aim for (it sets the z
  * chunk length); 0 fills one round of the workgroups the device holds at once.
  * inner_tol_exp is the FP32 inner-solve residual reduction 10^-inner_tol_exp of

@@ -2189,7 +2189,7 @@ void alofdft_destroy(alofdft_ctx* c) {
 }
 
 int alofdft_set_tuning(alofdft_ctx* c, int stencil_variant, int target_blocks, int inner_tol_exp) {
-  const bool var_ok = (stencil_variant >= -1 && stencil_variant <= 17) || (stencil_variant >= 100 && stencil_variant <= 117);
+  const bool var_ok = (stencil_variant >= -1 && stencil_variant <= 19) || (stencil_variant >= 100 && stencil_variant <= 119);
   if (!c || !var_ok || target_blocks < 0 || inner_tol_exp < 1 || inner_tol_exp > 7)
     return ALOFDFT_INVALID_ARGUMENT;
   c->variant = stencil_variant;

@@ -148,18 +148,17 @@ hipError_t launch_stencil_r(const LaunchCfg& lc, const Geom& g, const StencilW<T
         case 9: return launch_cfg2<T, R, 8, 2, 1, Op>(lc, g, W, op, nblocks, alt);
         case 10: return launch_cfg2<T, R, 2, 8, 1, Op>(lc, g, W, op, nblocks, alt);
         case 17: return launch_cfg2<T, R, 8, 1, 1, Op>(lc, g, W, op, nblocks, alt);
+        case 18: return launch_cfg2<T, R, 16, 1, 1, Op>(lc, g, W, op, nblocks, alt);
+        case 19: return launch_cfg2<T, R, 16, 2, 1, Op>(lc, g, W, op, nblocks, alt);
         default: break;
       }
     }
     // automatic: the pipelined iteration over 64x16 tiles of 8 waves (measured 3-4 %
     // faster at 63^3, 1 % at 109^3); the first half of schedule 1 over 64x8 tiles of 8 waves
     // of one row each (FP32 at 185^3: 31.2 us against 34.1 us for 4 waves of two rows, 11.6
-    // against 12.7 at 109^3), FP64 on large grids over 64x16 tiles of 8 waves (56.7 against
-    // 61.5 us at 185^3)
+    // against 12.7 at 109^3; FP64 53.7-58.4 against 61.5 at 185^3, 15.5 against 17.9 at
+    // 109^3; 16-wave tiles were slower for both)
     if constexpr (is_cg_pipe<Op>::value) return launch_cfg2<T, R, 8, 2, 1, Op>(lc, g, W, op, nblocks, alt);
-    if constexpr (std::is_same_v<Op, CGP1LOp<double>>) {
-      if ((long long)g.nx * g.ny * g.nz > 2000000ll) return launch_cfg2<T, R, 8, 2, 1, Op>(lc, g, W, op, nblocks, alt);
-    }
     if constexpr (std::is_same_v<Op, CGP1LOp<float>> || std::is_same_v<Op, CGP1LOp<double>>)
       return launch_cfg2<T, R, 8, 1, 1, Op>(lc, g, W, op, nblocks, alt);
     return launch_cfg2<T, R, 4, 2, 1, Op>(lc, g, W, op, nblocks, alt);
@@ -193,6 +192,9 @@ hipError_t launch_stencil_plain(const LaunchCfg& lc, const Geom& g, const Stenci
           case 14: return launch_cfg3<T, R, 8, 2, 1, Op>(lc, g, W, op, nblocks, alt);
           case 15: return launch_cfg3<T, R, 4, 4, 2, Op>(lc, g, W, op, nblocks, alt);
           case 16: return launch_cfg3<T, R, 8, 4, 1, Op>(lc, g, W, op, nblocks, alt);
+          case 17: return launch_cfg2<T, R, 8, 1, 1, Op>(lc, g, W, op, nblocks, alt);
+          case 18: return launch_cfg2<T, R, 16, 1, 1, Op>(lc, g, W, op, nblocks, alt);
+          case 19: return launch_cfg2<T, R, 16, 2, 1, Op>(lc, g, W, op, nblocks, alt);
           default: break;
         }
       }

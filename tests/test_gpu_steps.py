@@ -50,7 +50,8 @@ def test_stencil_fp32_matches_oracle(C, orc, nn):
 
 
 @pytest.mark.parametrize("target", [0, 16, 1024])
-@pytest.mark.parametrize("tuning", [-1, 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 105, 106, 111, 112])
+@pytest.mark.parametrize("tuning", [-1, 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 105,
+                                    106, 111, 112, 118, 119])
 def test_stencil_tile_variants(C, orc, tuning, target):
     # ragged in x, y and z; target 16 gives long z chunks (odd ones swept downwards),
     # target 1024 one-plane chunks
@@ -65,7 +66,7 @@ def test_stencil_tile_variants(C, orc, tuning, target):
     assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("tuning", [5, 6, 8, 10, 106, 11, 12, 13, 14, 15, 16])
+@pytest.mark.parametrize("tuning", [5, 6, 8, 10, 106, 11, 12, 13, 14, 15, 16, 17, 18, 19, 119])
 def test_stencil_tile_variants_fp32(C, orc, tuning):
     import torch
 
@@ -130,8 +131,8 @@ def test_poisson_matches_oracle(C, orc, bc, precision, schedule):
     assert np.abs(phi.cpu().numpy() - ref).max() <= 1e-8 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("schedule,tuning", [(2, 5), (2, 6), (2, 7), (2, 9), (2, 10), (2, 17), (1, 6), (1, 9),
-                                             (1, 10), (1, 17)])
+@pytest.mark.parametrize("schedule,tuning", [(2, 5), (2, 6), (2, 7), (2, 9), (2, 10), (2, 17), (2, 18), (2, 19),
+                                             (1, 6), (1, 9), (1, 10), (1, 17), (1, 18), (1, 19)])
 def test_poisson_cg_tile_variants(C, orc, schedule, tuning):
     # the CG kernels in every tile shape reach the oracle's solution (ragged 41x38x35 grid)
     g = synth.Grid((41, 38, 35), 0.45, (-9.0, -8.3, -7.6))
