@@ -42,7 +42,7 @@ class OrParams(C.Structure):
                 ("max_cg", C.c_int), ("sigma0", C.c_double), ("max_secant", C.c_int),
                 ("secant_rel", C.c_double), ("restart_every", C.c_int), ("tf_on", C.c_int),
                 ("hartree_on", C.c_int), ("vext", C.POINTER(C.c_double)), ("verbose", C.c_int),
-                ("al_stop", C.c_int), ("tol_energy", C.c_double), ("pseudo", C.c_int)]
+                ("al_stop", C.c_int), ("tol_energy", C.c_double), ("pseudo", C.c_int), ("domain", C.c_int)]
 
 
 class OrResult(C.Structure):
@@ -99,6 +99,11 @@ def lib():
         L.or_poisson_cg.argtypes = [C.POINTER(OrGrid), C.c_int, _DP, _DP, C.c_double, C.c_int,
                                     C.POINTER(C.c_int), _DP]
         L.or_evaluate.restype = C.c_int
+        L.or_poisson_cg_masked.argtypes = [C.POINTER(OrGrid), C.c_int, C.POINTER(C.c_ubyte), _DP, _DP,
+                                            C.c_double, C.c_int, C.POINTER(C.c_int), _DP]
+        L.or_domain_mask.argtypes = [C.POINTER(OrGrid), C.POINTER(C.c_ubyte)]
+        L.or_domain_mask.restype = None
+        L.or_domain_inside.argtypes = [C.POINTER(OrGrid), C.c_int, C.c_int, C.c_int]
         L.or_evaluate.argtypes = [C.POINTER(OrSystem), C.POINTER(OrParams), _DP, C.c_double, C.c_double,
                                   _DP, _DP, C.POINTER(OrEnergies), C.POINTER(C.c_long)]
         L.or_forces.argtypes = [C.POINTER(OrSystem), C.POINTER(OrParams), _DP, _DP]
@@ -266,14 +271,30 @@ def poisson_rhs(grid, n, bc, rho) -> np.ndarray:
     return out
 
 
-def poisson_cg(grid, n, rhs, phi0=None, tol=1e-10, maxit=100000):
+def poisson_cg(grid, n, rhs, phi0=None, tol=1e-10, maxit=100000, mask=None):
+    """CG on -(1/4pi) Delta_h phi = rhs; with a mask (uint8 grid array, e.g. domain_mask) the
+    unknowns are the masked nodes and phi is zero elsewhere."""
     rhs = _f64(rhs)
     phi = np.zeros_like(rhs) if phi0 is None else _f64(phi0).copy()
     it = C.c_int()
     rel = C.c_double()
     g = make_grid(grid)
-    st = lib().or_poisson_cg(C.byref(g), n, _p(rhs), _p(phi), tol, maxit, C.byref(it), C.byref(rel))
+    if mask is None:
+        st = lib().or_poisson_cg(C.byref(g), n, _p(rhs), _p(phi), tol, maxit, C.byref(it), C.byref(rel))
+    else:
+        m = np.ascontiguousarray(mask, dtype=np.uint8)
+        st = lib().or_poisson_cg_masked(C.byref(g), n, m.ctypes.data_as(C.POINTER(C.c_ubyte)), _p(rhs),
+                                        _p(phi), tol, maxit, C.byref(it), C.byref(rel))
     return phi, it.value, rel.value, st
+
+
+def domain_mask(grid):
+    """1 at the nodes of the ellipsoid inscribed in the box of nodes (Sec. 5.1), else 0;
+    indexed [k, j, i] like every grid array."""
+    g = make_grid(grid)
+    m = np.zeros((grid.n[2], grid.n[1], grid.n[0]), dtype=np.uint8)
+    lib().or_domain_mask(C.byref(g), m.ctypes.data_as(C.POINTER(C.c_ubyte)))
+    return m
 
 
 def evaluate(system, prm, u, eta=0.0, mu=0.0, phi=None):

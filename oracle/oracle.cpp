@@ -67,13 +67,15 @@ typedef struct {
   int al_stop;          // outer stopping rule: 0 = |C_h|/N < tol_constraint, 1 = |E_q - E_(q-1)|/M < tol_energy
   double tol_energy;    // Ha per atom (rule 1)
   int pseudo;           // pseudocharge: 0 = Gaussian b_J, 1 = -(1/4 pi) Delta_h V_J at the nodes
+  int domain;           // 0 = the box of nodes; 1 = the ellipsoid inscribed in it (Sec. 5.1): u and
+                        // phi are zero (Dirichlet) at every node outside it; needs bc = 0
 } OrParams;
 
 typedef struct {
   double E_total, E_TF, E_vW, E_xc, E_es, E_self, E_c, E_ext, L;
   double eta, C, gnorm, dE_last, poisson_relres;
   long al_iters, nlcg_iters, grad_evals, poisson_solves, cg_iters, matvecs;
-  int status;  // 0 converged, 1 iteration cap reached, -4 non-finite value
+  int status;  // 0 converged, 1 iteration cap reached, -4 non-finite value, -5 ellipsoid with bc != 0
 } OrResult;
 
 typedef struct {
@@ -98,6 +100,26 @@ static inline void pos(const OrGrid* g, int i, int j, int k, double x[3]) {
 static inline void centre(const OrGrid* g, double c[3]) {
   for (int a = 0; a < 3; ++a) c[a] = g->origin[a] + 0.5 * (g->n[a] - 1) * g->h;
 }
+// Sec. 5.1 (remark on the efficiency of the calculations): the Dirichlet conditions on u and
+// phi imposed on an ellipsoid inside the box instead of on the box.  reading: the ellipsoid
+// inscribed in the box of nodes, centre and semi-axes (n_a - 1) h / 2 per axis; a node on or
+// inside it is a free node, every other node a Dirichlet node with u = phi = 0.
+int or_domain_inside(const OrGrid* g, int i, int j, int k) {
+  const int idx[3] = {i, j, k};
+  double q = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    const double c = 0.5 * (g->n[a] - 1);
+    if (c > 0) q += ((idx[a] - c) / c) * ((idx[a] - c) / c);
+  }
+  return q <= 1.0 + 1e-12 ? 1 : 0;
+}
+
+void or_domain_mask(const OrGrid* g, unsigned char* mask) {
+  for (int k = 0; k < g->n[2]; ++k)
+    for (int j = 0; j < g->n[1]; ++j)
+      for (int i = 0; i < g->n[0]; ++i) mask[lin(g, i, j, k)] = (unsigned char)or_domain_inside(g, i, j, k);
+}
+
 static double dot(long n, const double* a, const double* b) {
   double s = 0.0;
 #pragma omp parallel for reduction(+ : s) schedule(static)
@@ -450,12 +472,22 @@ static void apply_A(const OrGrid* g, int n, const double* f, double* out) {
 // stopping at ||rhs - A phi||_2 < tol ||rhs||_2.
 // reading: the paper solves this symmetric positive definite system with GMRES;
 // CG reaches the same solution to the same tolerance.
+// With a mask (the active domain), the unknowns are the masked nodes only: phi is zero at
+// every other node, and the equations there are dropped (A restricted to the domain, which is
+// again symmetric positive definite).
 // Returns 0 on convergence, 1 at the iteration cap.  *iters = iterations taken.
-int or_poisson_cg(const OrGrid* g, int n, const double* rhs, double* phi, double tol, int maxit,
-                  int* iters, double* relres) {
+int or_poisson_cg_masked(const OrGrid* g, int n, const unsigned char* mask, const double* rhs, double* phi,
+                         double tol, int maxit, int* iters, double* relres) {
   long N = npts(g);
-  std::vector<double> r(N), p(N), Ap(N);
-  double bnorm = std::sqrt(dot(N, rhs, rhs));
+  std::vector<double> r(N), p(N), Ap(N), b(rhs, rhs + N);
+  auto restrict_to = [&](double* f) {
+    if (mask)
+      for (long i = 0; i < N; ++i)
+        if (!mask[i]) f[i] = 0.0;
+  };
+  restrict_to(b.data());
+  restrict_to(phi);
+  double bnorm = std::sqrt(dot(N, b.data(), b.data()));
   if (iters) *iters = 0;
   if (bnorm == 0.0) {
     std::fill(phi, phi + N, 0.0);
@@ -463,12 +495,14 @@ int or_poisson_cg(const OrGrid* g, int n, const double* rhs, double* phi, double
     return 0;
   }
   apply_A(g, n, phi, Ap.data());
-  for (long i = 0; i < N; ++i) r[i] = rhs[i] - Ap[i];
+  restrict_to(Ap.data());
+  for (long i = 0; i < N; ++i) r[i] = b[i] - Ap[i];
   p = r;
   double rr = dot(N, r.data(), r.data());
   int it = 0;
   while (std::sqrt(rr) >= tol * bnorm && it < maxit) {
     apply_A(g, n, p.data(), Ap.data());
+    restrict_to(Ap.data());
     double alpha = rr / dot(N, p.data(), Ap.data());
     for (long i = 0; i < N; ++i) {
       phi[i] += alpha * p[i];
@@ -485,6 +519,11 @@ int or_poisson_cg(const OrGrid* g, int n, const double* rhs, double* phi, double
   return std::sqrt(rr) < tol * bnorm ? 0 : 1;
 }
 
+int or_poisson_cg(const OrGrid* g, int n, const double* rhs, double* phi, double tol, int maxit, int* iters,
+                  double* relres) {
+  return or_poisson_cg_masked(g, n, nullptr, rhs, phi, tol, maxit, iters, relres);
+}
+
 // ---------------------------------------------------------------- energy and gradient
 struct Work {
   const OrSystem* sys;
@@ -492,6 +531,7 @@ struct Work {
   long N;
   double h3;
   std::vector<double> b, phi, lap, rho, rhs, jac;
+  std::vector<unsigned char> mask;  // active domain (empty: the whole box)
   double E_self, E_c;
   long grad_evals, poisson_solves, cg_iters, matvecs;
   double last_relres;
@@ -511,6 +551,11 @@ static void work_init(Work& W, const OrSystem* sys, const OrParams* prm) {
   W.jac.assign(W.N, 0.0);
   W.E_self = 0.0;
   W.E_c = 0.0;
+  W.mask.clear();
+  if (prm->domain == 1) {
+    W.mask.assign(W.N, 0);
+    or_domain_mask(&sys->grid, W.mask.data());
+  }
   if (prm->hartree_on) {
     or_pseudocharge(&sys->grid, sys->M, sys->R, sys->Z, prm->gauss_s, prm->r_cut, prm->pseudo, prm->fd_n,
                     W.b.data());
@@ -532,7 +577,8 @@ static void solve_phi(Work& W, const double* u) {
   or_poisson_rhs(&S->grid, P->fd_n, P->bc, W.rho.data(), W.rhs.data());
   int it = 0;
   double rel = 0.0;
-  int st = or_poisson_cg(&S->grid, P->fd_n, W.rhs.data(), W.phi.data(), P->tol_poisson, P->max_cg, &it, &rel);
+  int st = or_poisson_cg_masked(&S->grid, P->fd_n, W.mask.empty() ? nullptr : W.mask.data(), W.rhs.data(),
+                                W.phi.data(), P->tol_poisson, P->max_cg, &it, &rel);
   if (st != 0) W.poisson_capped++;
   W.poisson_solves++;
   W.cg_iters += it;
@@ -600,6 +646,7 @@ static void energy_gradient(Work& W, const double* u, double eta, double mu, dou
     if (P->hartree_on) veff += W.phi[i];
     if (P->vext) veff += P->vext[i];
     g[i] = -0.5 * P->lambda * W.lap[i] + veff * ui + shift * ui;
+    if (!W.mask.empty() && !W.mask[i]) g[i] = 0.0;  // u is fixed (zero) outside the domain
     // local diagonal of the residual's Jacobian (Jacobi preconditioner), with the
     // non-vW part clipped at zero: -3 lambda w_0 + max(0, (4/3)V_K + V_eff + shift)
     W.jac[i] = vw_diag + std::max(0.0, (4.0 / 3.0) * vk + veff + shift);
@@ -619,7 +666,10 @@ int or_evaluate(const OrSystem* sys, const OrParams* prm, const double* u, doubl
   Work W;
   work_init(W, sys, prm);
   if (phi_inout) std::memcpy(W.phi.data(), phi_inout, sizeof(double) * W.N);
-  evaluate(W, u, eta, mu, g, e);
+  std::vector<double> um(u, u + W.N);  // u is zero outside the active domain
+  for (long i = 0; i < (long)W.mask.size(); ++i)
+    if (!W.mask[i]) um[i] = 0.0;
+  evaluate(W, um.data(), eta, mu, g, e);
   if (phi_inout) std::memcpy(phi_inout, W.phi.data(), sizeof(double) * W.N);
   if (cg_iters) *cg_iters = W.cg_iters;
   return W.poisson_capped ? 1 : 0;
@@ -985,6 +1035,7 @@ void or_default_params(OrParams* p) {
   p->al_stop = 0;
   p->tol_energy = 3.6749e-6;  // 1e-4 eV per atom (Sec. 5.3.1), in Hartree
   p->pseudo = 0;
+  p->domain = 0;
 }
 
 // Ground state for fixed nuclei (Sec. 3, Algorithm AugLag, and Sec. 5.3.2 for
@@ -1003,6 +1054,12 @@ int or_solve(const OrSystem* sys, const OrParams* prm, const double* u0, double*
     res->status = -4;
     return -4;
   }
+  if (prm->domain == 1 && prm->bc != 0) {  // the ellipsoid takes zero Dirichlet values for phi
+    res->status = -5;
+    return -5;
+  }
+  for (long i = 0; i < (long)W.mask.size(); ++i)
+    if (!W.mask[i]) u[i] = 0.0;
   OrEnergies e;
   std::memset(&e, 0, sizeof(e));
   double gn = 0.0;

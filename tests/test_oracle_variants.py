@@ -100,3 +100,79 @@ def test_energy_change_stopping_rule(orc):
     assert a["status"] == 0 and b["status"] == 0
     assert b["al_iters"] >= 2 and abs(b["dE_last"]) / S.M < 1e-8
     assert abs(a["E_total"] - b["E_total"]) / S.M < 1e-8
+
+
+# ---------------------------------------------------------------- ellipsoidal active domain (Sec. 5.1)
+def test_domain_mask_is_the_inscribed_ellipsoid(orc):
+    # the nodes of the ellipsoid inscribed in the box of nodes: the count follows its volume
+    # (4/3) pi abc in index units up to a surface term, the mask has the box's reflection
+    # symmetries, holds the centre and the face centres and leaves out the corners
+    g = synth.Grid((41, 33, 25), 0.5, (0.0, 0.0, 0.0))
+    m = orc.domain_mask(g).astype(bool)
+    a, b, c = 20.0, 16.0, 12.0
+    vol = 4.0 / 3.0 * np.pi * a * b * c
+    assert abs(m.sum() - vol) < 0.05 * vol
+    assert np.array_equal(m, m[::-1, :, :]) and np.array_equal(m, m[:, ::-1, :]) and np.array_equal(m, m[:, :, ::-1])
+    assert m[12, 16, 20] and m[12, 16, 0] and m[12, 0, 20] and m[0, 16, 20]
+    assert not m[0, 0, 0] and not m[24, 32, 40]
+    k, j, i = np.nonzero(m)
+    assert np.all(((i - a) / a) ** 2 + ((j - b) / b) ** 2 + ((k - c) / c) ** 2 <= 1 + 1e-12)
+
+
+def test_masked_poisson_is_the_restricted_dense_solve(orc):
+    # A restricted to the domain (rows and columns of the free nodes), solved densely
+    g = synth.Grid((9, 8, 7), 0.6, (0.0, 0.0, 0.0))
+    n = 3
+    m = orc.domain_mask(g).reshape(-1).astype(bool)
+    N = m.size
+    A = np.zeros((N, N))
+    for col in range(N):
+        e = np.zeros(N)
+        e[col] = 1.0
+        A[:, col] = -orc.laplacian(g, n, e.reshape(g.n[2], g.n[1], g.n[0])).reshape(-1) / (4 * np.pi)
+    rng = np.random.default_rng(5)
+    rhs = rng.standard_normal(N)
+    idx = np.nonzero(m)[0]
+    ref = np.zeros(N)
+    ref[idx] = np.linalg.solve(A[np.ix_(idx, idx)], rhs[idx])
+    phi, its, rel, st = orc.poisson_cg(g, n, rhs.reshape(g.n[2], g.n[1], g.n[0]), tol=1e-13,
+                                       mask=m.reshape(g.n[2], g.n[1], g.n[0]))
+    assert st == 0
+    assert np.abs(phi.reshape(-1) - ref).max() < 1e-10 * np.abs(ref).max()
+    assert np.all(phi.reshape(-1)[~m] == 0.0)
+
+
+def test_uniform_sphere_potential_converges(orc):
+    # -(1/4 pi) Delta phi = 1 in a sphere of radius a, phi = 0 outside: phi(0) = (2 pi / 3) a^2.
+    # The stair-stepped Dirichlet surface makes the error first order in h (the first Dirichlet
+    # nodes lie beyond a, so it is positive)
+    a = 4.0
+    errs = []
+    for n in (17, 33, 65):
+        h = 2 * a / (n - 1)
+        g = synth.Grid((n, n, n), h, (-a, -a, -a))
+        m = orc.domain_mask(g)
+        phi, _, _, st = orc.poisson_cg(g, 6, m.astype(np.float64), tol=1e-12, mask=m)
+        assert st == 0
+        c = n // 2
+        errs.append((phi[c, c, c] - 2 * np.pi / 3 * a * a) / (2 * np.pi / 3 * a * a))
+    assert all(e > 0 for e in errs)
+    assert errs[0] < 0.06 and errs[1] < 0.6 * errs[0] and errs[2] < 0.6 * errs[1]
+
+
+def test_ellipsoid_domain_solve(orc):
+    # an atom at the centre of the box: the ellipsoid keeps u and phi zero outside it, the
+    # ground state stays close to the box's (the density decays long before the surface), and
+    # the ellipsoid with multipole values for phi is refused
+    S = synth.single_atom(L=16.0, n=21)
+    u0 = synth.initial_u(S.grid, S.N)
+    box = orc.solve(S, orc.params(bc=0), u0)
+    ell = orc.solve(S, orc.params(bc=0, domain=1), u0)
+    assert box["status"] == 0 and ell["status"] == 0
+    m = orc.domain_mask(S.grid).astype(bool)
+    assert np.all(ell["u"][~m] == 0.0) and np.all(ell["phi"][~m] == 0.0)
+    assert abs(ell["E_total"] - box["E_total"]) < 2e-3
+    assert abs(ell["E_total"] - box["E_total"]) > 1e-9  # the domain does change the problem
+    assert abs(S.grid.h ** 3 * np.sum(ell["u"] ** 2) - S.N) / S.N < 1e-8
+    bad = orc.solve(S, orc.params(bc=1, domain=1), u0)
+    assert bad["status"] == -5
