@@ -71,6 +71,14 @@ extern "C" {
 #define ALOFDFT_STOP_CONSTRAINT 0
 #define ALOFDFT_STOP_ENERGY_CHANGE 1
 
+/* computational domain: the box of nodes, or the ellipsoid inscribed in it (Sec. 5.1:
+ * Dirichlet conditions for u and phi on an ellipsoid inside the box): every node outside
+ * the ellipsoid (centre and semi-axes (n_a - 1) h / 2 per axis, nodes on its surface
+ * inside) is a Dirichlet node with u = phi = 0; the ellipsoid takes zero boundary values
+ * for phi (phi_bc = ALOFDFT_BC_ZERO) */
+#define ALOFDFT_DOMAIN_BOX 0
+#define ALOFDFT_DOMAIN_ELLIPSOID 1
+
 /* boundary values of phi: zero Dirichlet (Sec. 4) or the multipole expansion
  * (monopole + dipole + traceless quadrupole of u^2 + b about the box centre)
  * suggested in Sec. 5.1 */
@@ -120,6 +128,7 @@ typedef struct {
   double guess_floor;     /* atomic guess: uniform floor as a fraction of N/V (1e-3) */
   int al_stop;            /* ALOFDFT_STOP_* (default constraint) */
   double tol_energy;      /* energy-change rule, Ha per atom (3.6749e-6 = 1e-4 eV, Sec. 5.3.1) */
+  int domain;             /* ALOFDFT_DOMAIN_* (default box); ELLIPSOID needs phi_bc ZERO */
 } alofdft_params;
 
 typedef struct {

@@ -21,6 +21,7 @@ AL, PENALTY, LAGRANGE = 0, 1, 2
 PSEUDO_GAUSSIAN, PSEUDO_FD_LAPLACIAN = 0, 1
 GUESS_UNIFORM, GUESS_ATOMIC = 0, 1
 STOP_CONSTRAINT, STOP_ENERGY_CHANGE = 0, 1
+DOMAIN_BOX, DOMAIN_ELLIPSOID = 0, 1
 SERVER_SLOT_BLOCKS = 256  # ALOFDFT_SERVER_SLOT_BLOCKS: default workgroups per stencil launch of a server slot
 BC_ZERO, BC_MULTIPOLE = 0, 1
 FP64, FP32_REFINED = 0, 1
@@ -36,7 +37,7 @@ class Params(C.Structure):
                 ("secant_rel", C.c_double), ("restart_every", C.c_int), ("cg_check_every", C.c_int),
                 ("seed", C.c_uint64), ("pseudocharge", C.c_int), ("initial_guess", C.c_int),
                 ("guess_width", C.c_double), ("guess_floor", C.c_double), ("al_stop", C.c_int),
-                ("tol_energy", C.c_double)]
+                ("tol_energy", C.c_double), ("domain", C.c_int)]
 
 
 class SystemS(C.Structure):

@@ -23,7 +23,18 @@ struct Geom {
   long long plane; // px*py
   long long base;  // offset of interior (0,0,0)
   long long total; // px*py*pz
+  // active domain (Sec. 5.1): nullptr for the whole box, else for every interior row
+  // (j, k) the x range dom[2(j + ny k)] .. dom[2(j + ny k) + 1] of its free nodes (empty
+  // when the first exceeds the second); every other node is a Dirichlet node (zero)
+  const int* dom;
 };
+
+// Whether interior node (i, j, k) is a free node of the active domain.
+__host__ __device__ inline bool in_domain(const Geom& g, int i, int j, int k) {
+  if (!g.dom) return true;
+  const long long r = 2ll * ((long long)k * g.ny + j);
+  return i >= g.dom[r] && i <= g.dom[r + 1];
+}
 
 // Stencil coefficients scaled by a factor: c0 = 6 w_0 * scale, w[p] = w_p * scale.
 template <typename T>

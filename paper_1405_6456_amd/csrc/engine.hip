@@ -150,6 +150,7 @@ Geom make_geom(const int n[3], int R) {
   g.plane = (long long)g.px * g.py;
   g.base = (long long)R * g.plane + (long long)R * g.px + ox;
   g.total = g.plane * g.pz;
+  g.dom = nullptr;
   return g;
 }
 
@@ -961,6 +962,9 @@ void validate(alofdft_ctx* c, const alofdft_system* s, const alofdft_params* p) 
           "the atomic guess needs guess_width > 0 and guess_floor > 0");
   require(c, p->al_stop == ALOFDFT_STOP_CONSTRAINT || (p->al_stop == ALOFDFT_STOP_ENERGY_CHANGE && p->tol_energy > 0),
           "bad al_stop or tol_energy");
+  require(c, p->domain == ALOFDFT_DOMAIN_BOX || p->domain == ALOFDFT_DOMAIN_ELLIPSOID, "bad domain");
+  require(c, p->domain == ALOFDFT_DOMAIN_BOX || p->phi_bc == ALOFDFT_BC_ZERO,
+          "the ellipsoidal domain takes zero boundary values for phi (phi_bc = ALOFDFT_BC_ZERO)");
   require(c, p->mu0 > 0 && p->kappa > 0 && p->kappa < 1, "need mu0 > 0 and 0 < kappa < 1");
   require(c, p->phi_bc == ALOFDFT_BC_ZERO || p->phi_bc == ALOFDFT_BC_MULTIPOLE, "bad phi_bc");
   require(c, p->precision == ALOFDFT_FP64 || p->precision == ALOFDFT_FP32_REFINED, "bad precision");
@@ -1114,6 +1118,40 @@ uint64_t splitmix64(uint64_t state) {
   return z ^ (z >> 31);
 }
 
+// Active domain of Sec. 5.1: the ellipsoid inscribed in the box of nodes (centre and
+// semi-axes (n_a - 1)/2 in index units); a node is free when
+// sum_a ((i_a - c_a) / c_a)^2 <= 1 + 1e-12, summed over the axes in order, and every row
+// (j, k) of free nodes is one x range by convexity.  Device table of the ranges (Geom::dom).
+const int* domain_rows(alofdft_ctx* c, const int n[3]) {
+  const double cen[3] = {0.5 * (n[0] - 1), 0.5 * (n[1] - 1), 0.5 * (n[2] - 1)};
+  auto term = [&](int a, int idx) {
+    if (!(cen[a] > 0)) return 0.0;
+    const double t = (idx - cen[a]) / cen[a];
+    return t * t;
+  };
+  std::vector<int> rows(2 * (size_t)n[1] * n[2]);
+  for (int k = 0; k < n[2]; ++k)
+    for (int j = 0; j < n[1]; ++j) {
+      int lo = n[0], hi = -1;
+      for (int i = 0; i < n[0]; ++i) {
+        double q = 0.0;
+        q += term(0, i);
+        q += term(1, j);
+        q += term(2, k);
+        if (q <= 1.0 + 1e-12) {
+          lo = std::min(lo, i);
+          hi = std::max(hi, i);
+        }
+      }
+      rows[2 * ((size_t)k * n[1] + j)] = lo;
+      rows[2 * ((size_t)k * n[1] + j) + 1] = hi;
+    }
+  int* d = bufT<int>(c, "s.dom", rows.size());
+  HIPC(c, hipMemcpyAsync(d, rows.data(), rows.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  sync(c);  // rows is released on return
+  return d;
+}
+
 struct Eval {  // host copy of one evaluation's scalars
   double upd[kUpdRed];  // h^3-scaled
   double gr[G_NRED];    // raw sums
@@ -1124,6 +1162,7 @@ class Solver {
   Solver(alofdft_ctx* c, const alofdft_system* sys, const alofdft_params* prm)
       : c_(c), S_(sys), P_(prm) {
     g_ = make_geom(sys->n, prm->fd_half_width);
+    if (prm->domain == ALOFDFT_DOMAIN_ELLIPSOID) g_.dom = domain_rows(c, sys->n);
     h3_ = sys->h * sys->h * sys->h;
     const size_t T = g_.total;
     us_ = bufT<double>(c, "s.us", T);
@@ -1204,6 +1243,7 @@ class Solver {
     finalize(c_, partsU_, nU_, kUpdRed, h3_, upd);
     RhsOp<double> rop{v_, b_, rhs_, P_->phi_bc == ALOFDFT_BC_MULTIPOLE ? upd : nullptr, Wlap_, g_.R,
                       g_.nx, g_.ny, g_.nz, frame_, nullptr};
+    rop.dom = g_.dom;
     // RhsOp reads unscaled weights w[p]
     double w[kMaxRadius + 1];
     lap_weights(P_->fd_half_width, S_->h, w);
@@ -2140,6 +2180,7 @@ int alofdft_default_params(alofdft_params* p) {
   p->guess_floor = 1e-3;
   p->al_stop = ALOFDFT_STOP_CONSTRAINT;
   p->tol_energy = 3.6749e-6;
+  p->domain = ALOFDFT_DOMAIN_BOX;
   return ALOFDFT_OK;
 }
 

@@ -255,8 +255,9 @@ __global__ void __launch_bounds__(BX* BY) k_stencil(Geom g, StencilW<T> W, int z
             acc += W.w[p] * (((q[(s + R - p) % K][v] + q[(s + R + p) % K][v]) + (row[-p] + row[p])) + (ya + yb));
           }
           const int gy = gy0 + v;
-          if (gx < g.nx && gy < g.ny)
-            o.store(g.base + (long long)z * g.plane + (long long)gy * g.px + gx, gx, gy, z, c, acc, red);
+          if (gx < g.nx && gy < g.ny)  // Dirichlet nodes of an active domain: zero stencil value
+            o.store(g.base + (long long)z * g.plane + (long long)gy * g.px + gx, gx, gy, z, c,
+                    in_domain(g, gx, gy, z) ? acc : T(0), red);
         }
       }
     }
@@ -477,8 +478,9 @@ __global__ void __launch_bounds__(64 * BY) k_stencil2(Geom g, StencilW<T> W, int
       const int gx = x0 + lane, gy = y0 + wv * VY + v;
       // a lane outside the interior sits in the zero padding, where every input of the
       // op is zero: with the stencil value zeroed too, the op stores zeros there and
-      // adds nothing to its sums
-      const bool in = gy < g.ny && gx < g.nx;
+      // adds nothing to its sums.  The Dirichlet nodes of an active domain are treated
+      // alike (every array is zero there too).
+      const bool in = gy < g.ny && gx < g.nx && in_domain(g, gx, min(gy, g.ny - 1), z);
       if constexpr (NPRE > 0)
         o.storep(nb, vl, so + v * rowb, c, in ? acc : T(0), pre[s & 1][v], red);
       else
@@ -676,7 +678,9 @@ __global__ void __launch_bounds__(64 * BY) k_stencil3(Geom g, StencilW<T> W, int
             const int gx = x0 + lane, gy = y0 + wv * VY + v;
             if (gy < g.ny && gx < g.nx) {
               const T c = NEEDC ? cen[NEEDC ? (s - R + K) % K : 0][v] : T(0);
-              o.storeb(nb, vl, so + v * rowb, gx, gy, z, c, acc[(s - R + K) % K][v], red);
+              // Dirichlet nodes of an active domain store a zero stencil value (see k_stencil2)
+              const T a = in_domain(g, gx, gy, z) ? acc[(s - R + K) % K][v] : T(0);
+              o.storeb(nb, vl, so + v * rowb, gx, gy, z, c, a, red);
             }
           }
         }
@@ -1293,6 +1297,7 @@ struct RhsOp {
   BoxFrame f;
   double* parts_out;
   double mv[kUpdRed];  // this thread's copy of the moments
+  const int* dom = nullptr;  // active domain rows (see Geom::dom): zero right-hand side at Dirichlet nodes
   template <int NT>
   __device__ bool begin() {
     if (mom)
@@ -1300,6 +1305,13 @@ struct RhsOp {
     return true;
   }
   __device__ void apply(long long i, int ii, int jj, int kk, double*) const {
+    if (dom) {
+      const long long r = 2ll * ((long long)kk * ny + jj);
+      if (ii < dom[r] || ii > dom[r + 1]) {
+        rhs[i] = T(0);
+        return;
+      }
+    }
     double val = v[i] * v[i] + b[i];
     if (mom && (ii < R || jj < R || kk < R || ii >= nx - R || jj >= ny - R || kk >= nz - R)) {
       double dx, dy, dz;

@@ -217,6 +217,7 @@ __global__ void __launch_bounds__(256) k_pack(Geom g, const TS* dense, TD* padde
     const long long i = t % g.nx, j = (t / g.nx) % g.ny, k = t / ((long long)g.nx * g.ny);
     TS v = dense[t];
     if (absval) v = v < TS(0) ? -v : v;
+    if (!in_domain(g, (int)i, (int)j, (int)k)) v = TS(0);  // a Dirichlet node of the active domain
     padded[g.base + k * g.plane + j * g.px + i] = (TD)v;
   }
 }

@@ -186,3 +186,24 @@ def test_fcc10_fp32_refined_solution_is_the_oracle_minimiser(orc, capsys):
     assert abs(e["E_total"] - out["E_total"]) / S.M < 1e-9
     f_o = orc.forces(S, prm, phi_o)
     assert np.abs(f_o - out["forces"]).max() < 1e-6
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_ellipsoid_domain_solve_matches_oracle(C, orc, precision):
+    # the atom off the centre of a 16 Bohr box, the Dirichlet conditions on the inscribed
+    # ellipsoid (Sec. 5.1): the GPU's ground state equals the oracle's, with u and phi zero at
+    # every node outside
+    import paper_1405_6456_amd as lib
+
+    S = synth.single_atom(L=16.0, n=21)
+    S.R[0] += np.array([0.13, -0.07, 0.05])
+    u0 = synth.initial_u(S.grid, S.N)
+    ref = orc.solve(S, orc.params(bc=0, domain=1), u0)
+    out = C.solve(S, lib.default_params(phi_bc=0, domain=lib.DOMAIN_ELLIPSOID, precision=precision), u0)
+    assert ref["status"] == 0 and out["status"] == 0
+    m = orc.domain_mask(S.grid).astype(bool)
+    assert np.all(out["u"][~m] == 0.0) and np.all(out["phi"][~m] == 0.0)
+    etol = E_TOL_FP64 if precision == 0 else E_TOL_MIXED
+    assert abs(out["E_total"] - ref["E_total"]) / S.M < etol
+    assert np.abs(out["forces"] - ref["forces"]).max() < F_TOL
+    assert np.abs(out["u"] - ref["u"]).max() < 1e-5 * np.abs(ref["u"]).max()

@@ -408,3 +408,36 @@ def test_uniform_guess_matches_generator(C):
     S = synth.config("fcc2")
     ref = synth.initial_u(S.grid, S.N)
     assert np.abs(u - ref).max() <= 4e-16 * ref.max()
+
+
+# ---------------------------------------------------------------- ellipsoidal active domain (Sec. 5.1)
+@pytest.mark.parametrize("name", ["single", "fcc2"])
+def test_energy_gradient_in_ellipsoid_matches_oracle(C, orc, name):
+    # u and phi are zero at the Dirichlet nodes outside the inscribed ellipsoid; g vanishes
+    # there; phi, g and the energies match the oracle's element by element.  The row table the
+    # library builds reproduces the oracle's node mask exactly.
+    import paper_1405_6456_amd as lib
+
+    S = synth.config(name)
+    u = synth.initial_u(S.grid, S.N)
+    m = orc.domain_mask(S.grid).astype(bool)
+    eta, mu = -0.17, 0.8
+    g_ref, e_ref, phi_ref, _ = orc.evaluate(S, orc.params(bc=0, domain=1, tol_poisson=1e-12), u, eta, mu)
+    g, e, phi = C.energy_gradient(S, lib.default_params(phi_bc=0, domain=lib.DOMAIN_ELLIPSOID, tol_poisson=1e-12),
+                                  dev(u), eta, mu)
+    gd, pd = g.cpu().numpy(), phi.cpu().numpy()
+    assert np.all(pd[~m] == 0.0) and np.all(gd[~m] == 0.0)
+    assert np.abs(pd - phi_ref).max() <= 1e-8 * np.abs(phi_ref).max()
+    assert np.abs(gd - g_ref).max() <= 1e-8 * np.abs(g_ref).max()
+    for k in ("E_TF", "E_vW", "E_xc", "E_es", "E_total", "C", "L"):
+        kk = "C_h" if k == "C" else k
+        assert abs(e[kk] - e_ref[k]) <= 1e-9 * max(1.0, abs(e_ref[k])), k
+
+
+def test_ellipsoid_needs_zero_phi_boundary(C):
+    import paper_1405_6456_amd as lib
+
+    S = synth.single_atom(L=16.0, n=21)
+    with pytest.raises(lib.AlofdftError) as err:
+        C.solve(S, lib.default_params(phi_bc=lib.BC_MULTIPOLE, domain=lib.DOMAIN_ELLIPSOID), None)
+    assert err.value.status == lib.INVALID_ARGUMENT
