@@ -54,6 +54,9 @@ struct CGState {
   int done;        // 0 running, 1 converged, 2 non-finite, 3 zero rhs, 4 rounding breakdown
   int pad;
   long long done_iter;  // iteration whose prologue set done (iter must still equal it at the end)
+  long long halt;       // 1 + done_iter, written atomically with done (0 while running)
+  double xa[2];         // alpha of iteration k, indexed by k & 1: two-launch CG applies it to x
+                        // in the first half of iteration k + 1
 };
 
 // Multipole moments of u^2 + b about the box centre and the constraint sum,

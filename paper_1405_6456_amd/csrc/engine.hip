@@ -200,16 +200,18 @@ int launch_pw(alofdft_ctx* c, const Geom& g, const Op& op) {
   return nb;
 }
 
-// Second half of a CG iteration: one row per wave, at most kPointwiseBlocks blocks.
+// Second half of a CG iteration: one row per wave, at most kPointwiseBlocks blocks
+// (op.x null: r only, x is updated by the next first half).
 template <typename T>
 int launch_cg_update(alofdft_ctx* c, const Geom& g, const CGP2Op<T>& op, hipEvent_t ev_start = nullptr,
                      hipEvent_t ev_stop = nullptr) {
   const int rows = g.ny * g.nz;
   const int nb = std::max(1, std::min(kPointwiseBlocks, (rows + 3) / 4));
+  auto kern = op.x ? k_cg_update<T, 256, true> : k_cg_update<T, 256, false>;
   if (ev_start)  // the runtime stamps the events with the kernel's own start and end
-    hipExtLaunchKernelGGL((k_cg_update<T, 256>), dim3(nb), dim3(256), 0, c->stream, ev_start, ev_stop, 0, g, op);
+    hipExtLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, c->stream, ev_start, ev_stop, 0, g, op);
   else
-    hipLaunchKernelGGL((k_cg_update<T, 256>), dim3(nb), dim3(256), 0, c->stream, g, op);
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, c->stream, g, op);
   CHECK_LAUNCH(c);
   return nb;
 }
@@ -593,9 +595,13 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
       std::tie(e0, e1) = prof_pair(c, pool_used);
       std::tie(e2, e3) = prof_pair(c, pool_used + 1);
     }
-    const int nb1 = sched == 1 ? launch_stencil(c, g, A, CGP1LOp<T>{op1}, e0, e1)
-                                        : launch_stencil(c, g, A, op1, e0, e1);  // events stamp the kernel itself
-    CGP2Op<T> op2{x, r, op1.pnew, Ap, st, partsA, nb1, (int)k, partsB, T(0)};
+    // FP64 schedule 1 moves x += alpha p into the next first half
+    const bool defer_x = sched == 1 && CGP1LOp<T>::XD;
+    CGP1LOp<T> opl{op1};
+    opl.x = defer_x ? x : nullptr;
+    const int nb1 = sched == 1 ? launch_stencil(c, g, A, opl, e0, e1)
+                               : launch_stencil(c, g, A, op1, e0, e1);  // events stamp the kernel itself
+    CGP2Op<T> op2{defer_x ? nullptr : x, r, op1.pnew, Ap, st, partsA, nb1, (int)k, partsB, T(0)};
     nprev = launch_cg_update(c, g, op2, e2, e3);
     if (timed) {
       pending.push_back({k, pool_used});
@@ -635,7 +641,9 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
     CGP1Op<T> op1{r, pold, pnew, Ap, st, prev, nprev, nred_prev, (int)k, tol2, partsA, T(0)};
     if (sched == 1) {
       op1.pold = op1.pnew = p0;
-      launch_stencil(c, g, A, CGP1LOp<T>{op1});
+      CGP1LOp<T> opl{op1};
+      opl.x = CGP1LOp<T>::XD ? x : nullptr;  // FP64: also makes the pending x += alpha p
+      launch_stencil(c, g, A, opl);
     } else {
       launch_stencil(c, g, A, op1);
     }

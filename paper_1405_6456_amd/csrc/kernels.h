@@ -57,6 +57,13 @@ struct op_npre : std::integral_constant<int, 0> {};
 template <class Op>
 struct op_npre<Op, std::void_t<decltype(Op::NPRE)>> : std::integral_constant<int, Op::NPRE> {};
 
+// Ops with XPASS = true may leave their prologue in a mode (op.xonly) in which the
+// launch only runs op.xpass(g) over the grid instead of the stencil.
+template <class Op, class = void>
+struct op_xpass : std::false_type {};
+template <class Op>
+struct op_xpass<Op, std::void_t<decltype(Op::XPASS)>> : std::bool_constant<Op::XPASS> {};
+
 // Reduces acc[0..NRED) over the block; thread r < NRED writes component r to out[r].
 template <int NRED, int NT>
 __device__ inline void block_reduce_store(const double* acc, double* out) {
@@ -117,6 +124,20 @@ __device__ inline int block_read_done(const CGState* st) {
   return flag;
 }
 
+// The verdict with the iteration that reached it, as one word (1 + that iteration, 0
+// while running), so a block of iteration k can tell a verdict of an earlier launch
+// (halt <= k: stop) from one its own launch's block 0 has just written (halt = k + 1:
+// the block reaches the same verdict from the same sums itself).  Read like done.
+__device__ inline long long block_read_halt(const CGState* st) {
+  __shared__ long long flag;
+  if (threadIdx.x == 0) flag = ld_dev(&st->halt);
+  __syncthreads();
+  return flag;
+}
+__device__ inline void set_halt(CGState* st, long long k) {
+  __hip_atomic_store(&st->halt, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Logical block index such that the blocks the hardware places on one XCD
 // (physical index b = x mod 8) form one contiguous range of logical indices.
 __device__ inline int xcd_swizzle(int b, int nb) {
@@ -149,6 +170,12 @@ __global__ void __launch_bounds__(BX* BY) k_stencil(Geom g, StencilW<T> W, int z
 
   Op o = op;
   if (!o.template begin<NT>()) return;
+  if constexpr (op_xpass<Op>::value) {
+    if (o.xonly) {
+      o.xpass(g);
+      return;
+    }
+  }
 
   const int ntile = tiles_x * tiles_y;
   const int lb = xcd_swizzle(blockIdx.x, gridDim.x);
@@ -337,6 +364,12 @@ __global__ void __launch_bounds__(64 * BY) k_stencil2(Geom g, StencilW<T> W, int
   constexpr bool LATE = late_begin<Op>::value;
   if constexpr (!LATE) {
     if (!o.template begin<NT>()) return;
+    if constexpr (op_xpass<Op>::value) {
+      if (o.xonly) {
+        o.xpass(g);
+        return;
+      }
+    }
   }
 
   const uint32_t nb = (uint32_t)(g.total * (long long)ES);
@@ -440,6 +473,12 @@ __global__ void __launch_bounds__(64 * BY) k_stencil2(Geom g, StencilW<T> W, int
   load_pre(0, 0);
   if constexpr (LATE) {
     if (!o.template begin<NT>()) return;
+    if constexpr (op_xpass<Op>::value) {
+      if (o.xonly) {
+        o.xpass(g);
+        return;
+      }
+    }
   }
 
   auto step = [&](int s, int t) __attribute__((always_inline)) {
@@ -530,6 +569,12 @@ __global__ void __launch_bounds__(64 * BY) k_stencil3(Geom g, StencilW<T> W, int
 
   Op o = op;
   if (!o.template begin<NT>()) return;
+  if constexpr (op_xpass<Op>::value) {
+    if (o.xonly) {
+      o.xpass(g);
+      return;
+    }
+  }
 
   const uint32_t nb = (uint32_t)(g.total * (long long)ES);
   const int ntile = tiles_x * tiles_y;
@@ -777,7 +822,9 @@ struct CGInitOp {
 // Iteration k, first half: reduce r.r from the previous kernel's partials, stop
 // at r.r <= tol^2 ||rhs||^2, else p_new = r + beta p_old formed on load, Ap = A p_new,
 // reduce p.Ap.  Block 0 keeps the scalars in CGState (indexed by k parity so no
-// block reads a value written by the same launch).
+// block reads a value written by the same launch).  verdict(): 0 stop (a verdict of an
+// earlier launch, a zero right-hand side or a non-finite r.r), 1 iterate, 2 converged
+// in this launch.
 template <typename T>
 struct CGP1Op {
   static constexpr int NRED = 1;
@@ -793,8 +840,9 @@ struct CGP1Op {
   double* parts_out;
   T beta;
   template <int NT>
-  __device__ bool begin() {
-    if (block_read_done(st)) return false;
+  __device__ int verdict() {
+    const long long h = block_read_halt(st);
+    if (h != 0 && h <= k) return 0;
     const double rr = block_sum_parts<NT>(parts_in, nparts_in, nred_in, 0);
     double thresh;
     if (k == 0) {
@@ -805,8 +853,11 @@ struct CGP1Op {
         st->thresh = thresh;
       }
       if (rhs2 == 0.0) {
-        if (is_block0_thread0()) { st->done = 3; st->rr_last = rr; st->iter = 0; st->done_iter = 0; }
-        return false;
+        if (is_block0_thread0()) {
+          st->done = 3; st->rr_last = rr; st->iter = 0; st->done_iter = 0;
+          set_halt(st, 0);
+        }
+        return 0;
       }
     } else {
       thresh = ld_dev(&st->thresh);
@@ -818,16 +869,19 @@ struct CGP1Op {
         st->rr_last = rr;
         st->iter = k;
         st->done_iter = k;
+        set_halt(st, k);
       }
-      return false;
+      return bad ? 0 : 2;
     }
     beta = (k == 0) ? T(0) : (T)(rr / ld_dev(&st->rrh[(k - 1) & 1]));
     if (is_block0_thread0()) {
       st->rrh[k & 1] = rr;
       st->iter = k;
     }
-    return true;
+    return 1;
   }
+  template <int NT>
+  __device__ bool begin() { return verdict<NT>() == 1; }
   __device__ T load(long long i) const { return r[i] + beta * pold[i]; }
   __device__ void store(long long i, int, int, int, T c, T ap, double* red) const {
     pnew[i] = c;
@@ -850,19 +904,58 @@ struct CGP1Op {
 // place).  Same scalars and verdicts as CGP1Op, whose prologue it shares.  A p is
 // then a recurrence; its rounding is damped by beta < 1 and the solve's stopping
 // test uses the residual r itself.
+//
+// XD (FP64): the update x += alpha p of iteration k - 1 is made here too, where p_old is
+// loaded anyway, and the second half only updates r (10 array passes per iteration
+// instead of 11); alpha of iteration k - 1 comes from CGState::xa.  The launch in which
+// the solve converges has no p to form, so it only makes that last update of x (xonly,
+// op.xpass); launches queued after it stop in their prologue.  In FP32 the two extra
+// node operands cost the first half more than they save the second, so x stays there.
 template <typename T>
 struct CGP1LOp : CGP1Op<T> {
   static constexpr bool NEEDC = true;
   static constexpr bool LATE_BEGIN = true;  // the stencil input r needs no scalar
+  static constexpr bool XD = sizeof(T) == 8;
+  static constexpr bool XPASS = XD;
   using CGP1Op<T>::r;
   using CGP1Op<T>::pnew;
   using CGP1Op<T>::Ap;
   using CGP1Op<T>::k;
   using CGP1Op<T>::beta;
+  using CGP1Op<T>::st;
+  T* x;             // XD: the iterate (updated with alpha of iteration k - 1)
+  T xalpha;         // XD: alpha of iteration k - 1 (0 at k = 0)
+  bool xonly;       // XD: converged in this launch, only x += alpha p remains
+  template <int NT>
+  __device__ bool begin() {
+    const int v = this->template verdict<NT>();
+    if constexpr (!XD) {
+      return v == 1;
+    } else {
+      if (v == 0 || (v == 2 && k == 0)) return false;
+      xalpha = k == 0 ? T(0) : (T)ld_dev(&st->xa[(k - 1) & 1]);
+      xonly = v == 2;
+      return true;
+    }
+  }
+  // x += alpha p over the interior nodes, rows spread over all waves of the launch
+  __device__ void xpass(const Geom& g) const {
+    const int nw = gridDim.x * (blockDim.x >> 6);
+    const int nrows = g.ny * g.nz;
+    for (int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); row < nrows; row += nw) {
+      const int j = row % g.ny, kz = row / g.ny;
+      const long long rb = g.base + (long long)kz * g.plane + (long long)j * g.px;
+      for (int i = threadIdx.x & 63; i < g.nx; i += 64) x[rb + i] = x[rb + i] + xalpha * pnew[rb + i];
+    }
+  }
   __device__ T load(long long i) const { return r[i]; }
   __device__ void store(long long i, int, int, int, T c, T ar, double* red) const {
-    const T pn = k == 0 ? c : c + beta * pnew[i];
+    const T po = pnew[i];
+    const T pn = k == 0 ? c : c + beta * po;
     const T apn = k == 0 ? ar : ar + beta * Ap[i];
+    if constexpr (XD) {
+      if (k != 0) x[i] = x[i] + xalpha * po;
+    }
     pnew[i] = pn;
     Ap[i] = apn;
     red[0] += (double)pn * (double)apn;
@@ -871,30 +964,37 @@ struct CGP1LOp : CGP1Op<T> {
   __device__ void storeb(uint32_t nb, uint32_t vo, uint32_t so, int, int, int, T c, T ar, double* red) const {
     T pn = c, apn = ar;
     if (k != 0) {
-      pn = c + beta * bld((const T*)pnew, nb, vo, so);
+      const T po = bld((const T*)pnew, nb, vo, so);
+      pn = c + beta * po;
       apn = ar + beta * bld((const T*)Ap, nb, vo, so);
+      if constexpr (XD) bst(x, nb, vo, so, bld((const T*)x, nb, vo, so) + xalpha * po);
     }
     bst(pnew, nb, vo, so, pn);
     bst(Ap, nb, vo, so, apn);
     red[0] += (double)pn * (double)apn;
   }
-  // the same update with p_old and (A p)_old loaded a plane ahead (iteration 0 has no
-  // p_old: beta = 0 and the loaded values, whatever they hold, are not used)
-  static constexpr int NPRE = 2;
+  // the same update with p_old, (A p)_old (and x) loaded a plane ahead (iteration 0 has
+  // no p_old: beta = 0 and the loaded values, whatever they hold, are not used; x is
+  // stored back unchanged)
+  static constexpr int NPRE = XD ? 3 : 2;
   __device__ void prefetch(uint32_t nb, uint32_t vo, uint32_t so, T* pre) const {
     pre[0] = bld((const T*)pnew, nb, vo, so);
     pre[1] = bld((const T*)Ap, nb, vo, so);
+    if constexpr (XD) pre[2] = bld((const T*)x, nb, vo, so);
   }
   __device__ void storep(uint32_t nb, uint32_t vo, uint32_t so, T c, T ar, const T* pre, double* red) const {
     const T pn = k == 0 ? c : c + beta * pre[0];
     const T apn = k == 0 ? ar : ar + beta * pre[1];
     bst(pnew, nb, vo, so, pn);
     bst(Ap, nb, vo, so, apn);
+    if constexpr (XD) bst(x, nb, vo, so, k == 0 ? pre[2] : pre[2] + xalpha * pre[0]);
     red[0] += (double)pn * (double)apn;
   }
 };
 
-// Iteration k, second half: alpha = r.r / p.Ap; x += alpha p; r -= alpha Ap; reduce r.r.
+// Iteration k, second half: alpha = r.r / p.Ap; x += alpha p (x not null; else the
+// first half of iteration k + 1 makes it, with alpha kept in CGState::xa);
+// r -= alpha Ap; reduce r.r.
 template <typename T>
 struct CGP2Op {
   static constexpr int NRED = 1;
@@ -913,14 +1013,18 @@ struct CGP2Op {
     const double pap = block_sum_parts<NT>(parts_in, nparts_in, 1, 0);
     const double a = ld_dev(&st->rrh[k & 1]) / pap;
     if (!isfinite(a) || pap <= 0.0) {
-      if (is_block0_thread0()) { st->done = 2; st->iter = k; st->done_iter = k; }
+      if (is_block0_thread0()) {
+        st->done = 2; st->iter = k; st->done_iter = k;
+        set_halt(st, k);
+      }
       return false;
     }
     alpha = (T)a;
+    if (is_block0_thread0()) st->xa[k & 1] = a;
     return true;
   }
   __device__ void apply(long long i, int, int, int, double* red) const {
-    x[i] += alpha * p[i];
+    if (x) x[i] += alpha * p[i];
     const T ri = r[i] - alpha * Ap[i];
     r[i] = ri;
     red[0] += (double)ri * (double)ri;
@@ -931,8 +1035,9 @@ struct CGP2Op {
 // issues the loads of all its nodes of the row (up to 4 x 64 per pass) before any
 // store, so a row costs one memory latency.  The first row's loads go out before
 // the prologue that reduces p.Ap (they do not depend on alpha), so the two
-// latencies overlap.
-template <typename T, int NT>
+// latencies overlap.  XU = false: x is left to the next first half (op.x null), and
+// only r and A p are read.
+template <typename T, int NT, bool XU>
 __global__ void __launch_bounds__(NT) k_cg_update(Geom g, CGP2Op<T> op) {
   CGP2Op<T> o = op;
   double red[1] = {0.0};
@@ -949,8 +1054,10 @@ __global__ void __launch_bounds__(NT) k_cg_update(Geom g, CGP2Op<T> op) {
     for (int u = 0; u < 4; ++u) {
       const int i = i0 + lane + 64 * u;
       if (i < g.nx) {
-        xv[u] = x[rb + i];
-        pv[u] = p[rb + i];
+        if constexpr (XU) {
+          xv[u] = x[rb + i];
+          pv[u] = p[rb + i];
+        }
         rv[u] = r[rb + i];
         av[u] = Ap[rb + i];
       }
@@ -972,7 +1079,7 @@ __global__ void __launch_bounds__(NT) k_cg_update(Geom g, CGP2Op<T> op) {
       for (int u = 0; u < 4; ++u) {
         const int i = i0 + lane + 64 * u;
         if (i < g.nx) {
-          x[rb + i] = xv[u] + alpha * pv[u];
+          if constexpr (XU) x[rb + i] = xv[u] + alpha * pv[u];
           const T ri = rv[u] - alpha * av[u];
           r[rb + i] = ri;
           red[0] += (double)ri * (double)ri;
