@@ -41,9 +41,10 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 METRIC = "Gpts/s stencil (%HBM peak); AL-OFDFT solves/s, p50/p99 latency vs FP64"
-# algorithmic bytes per node: a stencil application reads x once and writes y once; a fused
-# CG iteration makes about ten passes over arrays (read r, p, A p and write p, A p in the
-# first launch; read x, r, p, A p and write x, r in the second, counted as 4 + 6 arrays)
+# algorithmic bytes per node: a stencil application reads x once and writes y once; a CG
+# iteration is counted as ten array passes, 8 reads and 2 writes of a fused iteration (the
+# two launches make 11 in FP32: read r, p, A p and write p, A p, then read x, r, p, A p and
+# write x, r; 10 in FP64, whose first launch also makes the previous x += alpha p)
 STENCIL_BYTES = {8: 16, 4: 8}
 CG_ITER_BYTES = {8: 80, 4: 40}
 
