@@ -132,7 +132,7 @@ def test_poisson_matches_oracle(C, orc, bc, precision, schedule):
 
 
 @pytest.mark.parametrize("schedule,tuning", [(2, 5), (2, 6), (2, 7), (2, 9), (2, 10), (2, 17), (2, 18), (2, 19),
-                                             (1, 6), (1, 9), (1, 10), (1, 17), (1, 18), (1, 19)])
+                                             (1, 6), (1, 9), (1, 10), (1, 11), (1, 14), (1, 17), (1, 18), (1, 19)])
 def test_poisson_cg_tile_variants(C, orc, schedule, tuning):
     # the CG kernels in every tile shape reach the oracle's solution (ragged 41x38x35 grid)
     g = synth.Grid((41, 38, 35), 0.45, (-9.0, -8.3, -7.6))
@@ -251,6 +251,26 @@ def test_poisson_one_reduction_iterates_follow_cg(C, orc, schedule):
             C.set_cg_schedule(-1)
     for a, b in zip(out[1], out[schedule]):
         assert np.abs(a - b).max() <= 1e-9 * np.abs(a).max()
+
+
+@pytest.mark.parametrize("schedule", [0, 1, 2])
+def test_poisson_capped_iterates_match_oracle_cg(C, orc, schedule):
+    # with the cap at k the returned phi is the k-th CG iterate from zero: the oracle's plain
+    # CG stopped at the same k (FP64; the two-launch schedule makes x += alpha p of its last
+    # iteration in the launch that tests the final residual)
+    g = synth.Grid((37, 34, 31), 0.5, (0.0, 0.0, 0.0))
+    rho = synth.random_field(g, 24)
+    rhs = orc.poisson_rhs(g, 6, 0, rho)
+    C.set_cg_schedule(schedule)
+    try:
+        got = {k: C.poisson(dev(rho), g, bc=0, precision=0, tol=1e-14, max_cg=k) for k in (1, 5, 20)}
+    finally:
+        C.set_cg_schedule(-1)
+    for k, (phi, its, rel) in got.items():
+        ref, rits, rrel, _ = orc.poisson_cg(g, 6, rhs, tol=1e-14, maxit=k)
+        assert its == k and rits == k
+        assert abs(rel - rrel) <= 1e-8 * rrel
+        assert np.abs(phi.cpu().numpy() - ref).max() <= 1e-9 * np.abs(ref).max()
 
 
 # ---------------------------------------------------------------- nuclei
