@@ -359,7 +359,10 @@ int alofdft_set_tuning(alofdft_ctx* ctx, int stencil_variant, int target_blocks,
  *   0  p = r + beta p formed on load (the stencil input is r and p over every
  *      tile's halo), A p by the stencil, p.Ap;
  *   1  A r by the stencil (one input array), then p = r + beta p and
- *      A p = A r + beta A p updated in place at each node, p.Ap.
+ *      A p = A r + beta A p updated in place at each node, p.Ap.  In FP64 this
+ *      launch also makes x += alpha p of the previous iteration (p is loaded there
+ *      anyway) and the second launch updates only r; the launch that finds the
+ *      solve converged makes the last x update.
  *   2  one launch and one reduction per iteration, pipelined form (Chronopoulos-
  *      Gear scalars, Ghysels-Vanroose recurrences): w = A r, s = A p and z = A s
  *      are kept as vectors, the stencil is applied to the stored w (m = A w), then
@@ -377,8 +380,9 @@ int alofdft_set_cg_schedule(alofdft_ctx* ctx, int schedule);
 
 /* Measurement of the dominant kernels.  With sample_every > 0, every
  * sample_every-th conjugate-gradient iteration has each of its launches (schedules
- * 0 and 1: the stencil launch -- A r, p, A p and p.Ap with schedule 1; p = r + beta p,
- * A p and p.Ap with schedule 0 -- and the update x += alpha p, r -= alpha A p, r.r;
+ * 0 and 1: the stencil launch -- A r, p, A p and p.Ap with schedule 1 (and the
+ * previous x += alpha p in FP64); p = r + beta p, A p and p.Ap with schedule 0 -- and
+ * the update x += alpha p (not in FP64 with schedule 1), r -= alpha A p, r.r;
  * schedule 2: the single pipelined launch) carry a pair of HIP events that the
  * runtime stamps with the start and end of the kernel itself (hipExtLaunchKernel),
  * so the means are the kernel durations a kernel trace reports; iterations launched
