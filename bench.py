@@ -493,7 +493,9 @@ def large_mode():
     """The size of the paper's largest cluster on one device: 29^3 fcc cells (97 556 atoms),
     474^3 = 106.5 M nodes: the pseudocharge of all atoms, Poisson solves (multipole boundary
     values, 1e-10, from zero) of u0^2 + b with the atomic-density guess in FP64 and
-    FP32-refined with their CG-iteration roofline, and the plain stencil at that size."""
+    FP32-refined with their CG-iteration roofline, one pass of the hot path (as the default
+    line: one AL step with two nonlinear-CG steps, energies and forces) in both precisions
+    with their agreement, and the plain stencil at that size."""
     import torch
 
     import paper_1405_6456_amd as lib
@@ -525,6 +527,28 @@ def large_mode():
                           "wall_s": round(wall, 3), "us_per_iter": round(1e6 * wall / max(1, its), 1),
                           "roofline": roof}), flush=True)
         del phi
+    del rho, b
+    u0 = ctx.initial_guess(S, lib.default_params(initial_guess=lib.GUESS_ATOMIC))
+    res = {}
+    for prec, name in ((lib.FP32_REFINED, "f32r"), (lib.FP64, "f64")):
+        ctx.profile_cg_kernel(64)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        o = ctx.solve_device(S, lib.default_params(precision=prec, max_outer=1, max_inner=2), u0, want_forces=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        roof = cg_roofline(ctx, lib, prec, f"cg_{'f32' if prec == lib.FP32_REFINED else 'f64'}_fcc29")
+        ctx.profile_cg_kernel(0)
+        res[name] = o
+        mv = o["matvec_fp64"] + o["matvec_fp32"]
+        print(json.dumps({"mode": "large", "step": f"pass_{name}", "wall_s": round(wall, 3),
+                          "gpts": round(mv * g.npts / wall / 1e9, 2), "E_per_atom": o["E_total"] / S.M,
+                          "inner": o["inner"], "poisson_solves": o["poisson_solves"], "cg_iters": o["cg_iters"],
+                          "roofline": roof}), flush=True)
+    print(json.dumps({"mode": "large", "step": "pass_agreement",
+                      "E_per_atom": abs(res["f32r"]["E_total"] - res["f64"]["E_total"]) / S.M,
+                      "F_max": float(abs(res["f32r"]["forces"] - res["f64"]["forces"]).max())}), flush=True)
+    del u0
     print(json.dumps({"mode": "large", "step": "stencil", **stencil_streaming(ctx, g.n, reps=10)}), flush=True)
     ctx.close()
 
