@@ -321,6 +321,23 @@ def test_largest_cluster_pseudocharge_and_poisson(C, orc):
     assert rel <= 1e-10 and its < 20000, (its, rel)
 
 
+def test_largest_cluster_hot_path_pass_precisions_agree(C):
+    # one pass of the hot path at 474^3 (one AL step, two NLCG steps with their
+    # warm-started solves, energies, forces): the FP32-refined path against the FP64 one
+    import paper_1405_6456_amd as lib
+
+    S = synth.config("fcc29")
+    u0 = C.initial_guess(S, lib.default_params(initial_guess=lib.GUESS_ATOMIC))
+    out = {p: C.solve_device(S, lib.default_params(precision=p, max_outer=1, max_inner=2), u0, want_forces=True)
+           for p in (lib.FP64, lib.FP32_REFINED)}
+    del u0
+    a, b = out[lib.FP64], out[lib.FP32_REFINED]
+    assert a["inner"] == 2 and b["inner"] == 2
+    assert abs(a["E_total"] - b["E_total"]) / S.M <= 1e-9
+    assert np.abs(a["forces"] - b["forces"]).max() <= 1e-6
+    assert np.isfinite(a["forces"]).all() and np.abs(a["forces"]).max() > 0
+
+
 @pytest.mark.parametrize("name", ["single", "fcc2"])
 def test_forces_given_phi(C, orc, name):
     S = synth.config(name)
