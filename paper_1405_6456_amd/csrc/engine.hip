@@ -208,6 +208,9 @@ int launch_cg_update(alofdft_ctx* c, const Geom& g, const CGP2Op<T>& op, hipEven
   const int rows = g.ny * g.nz;
   const int nb = std::max(1, std::min(kPointwiseBlocks, (rows + 3) / 4));
   auto kern = op.x ? k_cg_update<T, 256, true> : k_cg_update<T, 256, false>;
+  if constexpr (sizeof(T) == 4) {
+    if (op.paired) kern = k_cg_update<T, 256, true, true>;
+  }
   if (ev_start)  // the runtime stamps the events with the kernel's own start and end
     hipExtLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, c->stream, ev_start, ev_stop, 0, g, op);
   else
@@ -535,10 +538,26 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
     return cg_solve_pipe<T>(c, g, A, rhs, x, tol, max_it, check_every, tag, init, init_parts, init_nparts,
                             stop_on_stagnation, first_poll);
   const std::string t(tag);
+  // FP32 schedule 1 keeps p and A p interleaved: one 8-byte access per node for the pair
+  const bool paired = sched == 1 && sizeof(T) == 4 && 8 * g.total < (1ll << 32);
   T* r = gridbuf<T>(c, t + ".r", g);
   T* p0 = gridbuf<T>(c, t + ".p0", g);
   T* p1 = sched == 0 ? gridbuf<T>(c, t + ".p1", g) : p0;
-  T* Ap = gridbuf<T>(c, t + ".Ap", g);
+  T* Ap = paired ? nullptr : gridbuf<T>(c, t + ".Ap", g);
+  T* pa = paired ? reinterpret_cast<T*>(gridbuf<double>(c, t + ".pa", g)) : nullptr;  // 2 x total
+  // first half of schedule 1 (interleaved pairs, or x made here in FP64, or neither)
+  auto launch_first = [&](const CGP1Op<T>& op1, hipEvent_t ea, hipEvent_t eb) -> int {
+    if constexpr (sizeof(T) == 4) {
+      if (paired) {
+        CGP1LIOp opi{op1};
+        opi.pa = pa;
+        return launch_stencil(c, g, A, opi, ea, eb);
+      }
+    }
+    CGP1LOp<T> opl{op1};
+    opl.x = CGP1LOp<T>::XD ? x : nullptr;  // FP64: also makes the pending x += alpha p
+    return launch_stencil(c, g, A, opl, ea, eb);
+  };
   const int maxsb = max_stencil_blocks(g, c->target_blocks);
   double* partsI = bufT<double>(c, t + ".partsI", (size_t)std::max(maxsb, kPointwiseBlocks) * 2);
   double* partsA = bufT<double>(c, t + ".partsA", (size_t)maxsb);
@@ -597,11 +616,10 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
     }
     // FP64 schedule 1 moves x += alpha p into the next first half
     const bool defer_x = sched == 1 && CGP1LOp<T>::XD;
-    CGP1LOp<T> opl{op1};
-    opl.x = defer_x ? x : nullptr;
-    const int nb1 = sched == 1 ? launch_stencil(c, g, A, opl, e0, e1)
+    const int nb1 = sched == 1 ? launch_first(op1, e0, e1)
                                : launch_stencil(c, g, A, op1, e0, e1);  // events stamp the kernel itself
-    CGP2Op<T> op2{defer_x ? nullptr : x, r, op1.pnew, Ap, st, partsA, nb1, (int)k, partsB, T(0)};
+    CGP2Op<T> op2{defer_x ? nullptr : x, r, paired ? pa : op1.pnew, Ap, st, partsA, nb1, (int)k, partsB, T(0)};
+    op2.paired = paired ? 1 : 0;
     nprev = launch_cg_update(c, g, op2, e2, e3);
     if (timed) {
       pending.push_back({k, pool_used});
@@ -641,9 +659,7 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
     CGP1Op<T> op1{r, pold, pnew, Ap, st, prev, nprev, nred_prev, (int)k, tol2, partsA, T(0)};
     if (sched == 1) {
       op1.pold = op1.pnew = p0;
-      CGP1LOp<T> opl{op1};
-      opl.x = CGP1LOp<T>::XD ? x : nullptr;  // FP64: also makes the pending x += alpha p
-      launch_stencil(c, g, A, opl);
+      launch_first(op1, nullptr, nullptr);
     } else {
       launch_stencil(c, g, A, op1);
     }

@@ -330,6 +330,19 @@ __device__ inline void bst<double>(double* p, uint32_t nb, uint32_t vo, uint32_t
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), brsrc(p, nb), (int)vo, (int)so,
                                         ALOFDFT_STORE_POLICY);
 }
+// p and A p of one node side by side (the interleaved FP32 CG layout), moved by one
+// 8-byte access; the byte offsets are those of the pair array
+struct PApair {
+  float p, ap;
+};
+__device__ inline PApair bldpair(const float* pa, uint32_t nb, uint32_t vo, uint32_t so) {
+  return __builtin_bit_cast(PApair, __builtin_amdgcn_raw_buffer_load_b64(brsrc(pa, nb), (int)vo, (int)so, 0));
+}
+__device__ inline void bstpair(float* pa, uint32_t nb, uint32_t vo, uint32_t so, PApair v) {
+  using u2 = uint32_t __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), brsrc(pa, nb), (int)vo, (int)so,
+                                        ALOFDFT_STORE_POLICY);
+}
 
 // Same computation as k_stencil with a different schedule for large planes.  The
 // block is BY waves; wave w owns VY consecutive rows of a 64 x (BY*VY) tile and lane
@@ -992,6 +1005,49 @@ struct CGP1LOp : CGP1Op<T> {
   }
 };
 
+// The FP32 first half of schedule 1 (as CGP1LOp<float>) with p and A p interleaved in one
+// array, pa[2i] = p_i and pa[2i + 1] = (A p)_i: each node operand pair is one 8-byte
+// load and one 8-byte store instead of two 4-byte ones.  The pair array must stay below
+// 4 GiB (the caller checks).
+struct CGP1LIOp : CGP1Op<float> {
+  static constexpr bool NEEDC = true;
+  static constexpr bool LATE_BEGIN = true;  // the stencil input r needs no scalar
+  float* pa;
+  __device__ float load(long long i) const { return r[i]; }
+  __device__ void store(long long i, int, int, int, float c, float ar, double* red) const {
+    const float pn = k == 0 ? c : c + beta * pa[2 * i];
+    const float apn = k == 0 ? ar : ar + beta * pa[2 * i + 1];
+    pa[2 * i] = pn;
+    pa[2 * i + 1] = apn;
+    red[0] += (double)pn * (double)apn;
+  }
+  __device__ float loadb(uint32_t nb, uint32_t vo, uint32_t so) const { return bld(r, nb, vo, so); }
+  __device__ void storeb(uint32_t nb, uint32_t vo, uint32_t so, int, int, int, float c, float ar,
+                         double* red) const {
+    PApair v{c, ar};
+    if (k != 0) {
+      const PApair o = bldpair(pa, 2 * nb, 2 * vo, 2 * so);
+      v = PApair{c + beta * o.p, ar + beta * o.ap};
+    }
+    bstpair(pa, 2 * nb, 2 * vo, 2 * so, v);
+    red[0] += (double)v.p * (double)v.ap;
+  }
+  // the pair loaded a plane ahead (iteration 0: not used)
+  static constexpr int NPRE = 2;
+  __device__ void prefetch(uint32_t nb, uint32_t vo, uint32_t so, float* pre) const {
+    const PApair o = bldpair(pa, 2 * nb, 2 * vo, 2 * so);
+    pre[0] = o.p;
+    pre[1] = o.ap;
+  }
+  __device__ void storep(uint32_t nb, uint32_t vo, uint32_t so, float c, float ar, const float* pre,
+                         double* red) const {
+    const float pn = k == 0 ? c : c + beta * pre[0];
+    const float apn = k == 0 ? ar : ar + beta * pre[1];
+    bstpair(pa, 2 * nb, 2 * vo, 2 * so, PApair{pn, apn});
+    red[0] += (double)pn * (double)apn;
+  }
+};
+
 // Iteration k, second half: alpha = r.r / p.Ap; x += alpha p (x not null; else the
 // first half of iteration k + 1 makes it, with alpha kept in CGState::xa);
 // r -= alpha Ap; reduce r.r.
@@ -1007,6 +1063,7 @@ struct CGP2Op {
   int nparts_in, k;
   double* parts_out;
   T alpha;
+  int paired;  // 1: p points to the interleaved (p, A p) pairs and Ap is unused (FP32)
   template <int NT>
   __device__ bool begin() {
     if (block_read_done(st)) return false;
@@ -1036,9 +1093,10 @@ struct CGP2Op {
 // store, so a row costs one memory latency.  The first row's loads go out before
 // the prologue that reduces p.Ap (they do not depend on alpha), so the two
 // latencies overlap.  XU = false: x is left to the next first half (op.x null), and
-// only r and A p are read.
-template <typename T, int NT, bool XU>
+// only r and A p are read.  PI: p and A p come interleaved (op.paired, FP32).
+template <typename T, int NT, bool XU, bool PI = false>
 __global__ void __launch_bounds__(NT) k_cg_update(Geom g, CGP2Op<T> op) {
+  static_assert(!PI || (XU && sizeof(T) == 4), "interleaved pairs: FP32 with x updated here");
   CGP2Op<T> o = op;
   double red[1] = {0.0};
   const int lane = threadIdx.x & 63;
@@ -1054,12 +1112,19 @@ __global__ void __launch_bounds__(NT) k_cg_update(Geom g, CGP2Op<T> op) {
     for (int u = 0; u < 4; ++u) {
       const int i = i0 + lane + 64 * u;
       if (i < g.nx) {
-        if constexpr (XU) {
+        if constexpr (PI) {
+          const PApair o = reinterpret_cast<const PApair*>(p)[rb + i];
+          pv[u] = o.p;
+          av[u] = o.ap;
           xv[u] = x[rb + i];
-          pv[u] = p[rb + i];
+        } else {
+          if constexpr (XU) {
+            xv[u] = x[rb + i];
+            pv[u] = p[rb + i];
+          }
+          av[u] = Ap[rb + i];
         }
         rv[u] = r[rb + i];
-        av[u] = Ap[rb + i];
       }
     }
   };
