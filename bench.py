@@ -115,7 +115,8 @@ def traffic_for(key, path=TRAFFIC_JSON):
 
 def summarize_counters(fetch_csv, write_csv, key, path=TRAFFIC_JSON):
     """Bytes per CG iteration of the FP32 CG kernels (the stencil launch k_stencil2<float, ...,
-    CGP1LOp<float>> and the update k_cg_update<float>) from a FETCH_SIZE pass and a WRITE_SIZE
+    CGP1LIOp> -- CGP1LOp<float> before p and A p were interleaved -- and the update
+    k_cg_update<float>) from a FETCH_SIZE pass and a WRITE_SIZE
     pass (KiB per dispatch) of --mode counters, each scaled by what the same counter reads for
     the reference copy of 256 MiB in that run (FETCH_SIZE counts a 128-byte read request of
     this part as 64 bytes: its copy reads 128 MiB of the 256).  Updates profiles/traffic.json."""
@@ -133,7 +134,8 @@ def summarize_counters(fetch_csv, write_csv, key, path=TRAFFIC_JSON):
     res = {}
     for csv_path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
         pk = per_kernel(csv_path, counter)
-        st = [v for k, vs in pk.items() if "CGP1LOp<float>" in k and "k_stencil" in k for v in vs]
+        st = [v for k, vs in pk.items() if ("CGP1LOp<float>" in k or "CGP1LIOp" in k) and "k_stencil" in k
+              for v in vs]
         up = [v for k, vs in pk.items() if "k_cg_update<float" in k for v in vs]
         cp = [v for k, vs in pk.items() if "copyBuffer" in k or "elementwise" in k for v in vs]
         cp = [v for v in cp if v > 0.5 * max(cp)] if cp else []
@@ -221,7 +223,8 @@ def cg_roofline(ctx, lib, prec, key):
     n, ms, pts, sched, first, second = ctx.cg_kernel_stats(dt_idx, split=True)
     alg = CG_ITER_BYTES[es] * pts
     achieved = alg / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-    names = {0: "k_stencil2<CGP1Op> + k_cg_update", 1: "k_stencil2<CGP1LOp> + k_cg_update",
+    names = {0: "k_stencil2<CGP1Op> + k_cg_update",
+             1: "k_stencil2<CGP1LIOp> + k_cg_update" if es == 4 else "k_stencil2<CGP1LOp> + k_cg_update",
              2: "k_stencil2<CGPipeOp>"}
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(key),
