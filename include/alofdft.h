@@ -204,7 +204,9 @@ void alofdft_destroy(alofdft_ctx* ctx);
  *              FD gradient of Sec. 4) plus the Appendix-A overlap correction.
  *   res        required.
  * Errors: INVALID_ARGUMENT for h <= 0, fd_half_width outside 1..8, n < 2n+1,
- * M < 1, N <= 0, an atom whose r_cut ball leaves the box, non-finite input;
+ * a grid whose padded FP64 array would reach 4 GiB (the kernels address arrays
+ * with 32-bit byte offsets: cubes up to 768^3 nodes at n = 6), M < 1, N <= 0, an
+ * atom whose r_cut ball leaves the box, non-finite input;
  * OUT_OF_MEMORY; DEVICE_ERROR; NUMERICAL when a non-finite value appears. */
 int alofdft_solve(alofdft_ctx* ctx, const alofdft_system* sys, const alofdft_params* prm, const double* u0,
                   double* u_out, double* phi_out, double* forces_out, alofdft_result* res);
@@ -281,7 +283,8 @@ int alofdft_apply_laplacian_noalloc(alofdft_ctx* ctx, const int n[3], double h, 
  * `precision` (ALOFDFT_FP64 / FP32_REFINED) from the guess in phi_dev to
  * ||rhs - A phi||_2 < tol ||rhs||_2.  rho_dev, phi_dev: device grid arrays.
  * *iters (nullable) receives the CG iterations; *relres (nullable) the final
- * relative residual.  NOT_CONVERGED at max_cg. */
+ * relative residual.  NOT_CONVERGED at max_cg.  INVALID_ARGUMENT for bad
+ * arguments and for grids beyond the 4 GiB array limit of alofdft_solve. */
 int alofdft_poisson(alofdft_ctx* ctx, const int n[3], double h, const double origin[3], int fd_half_width,
                     int bc, int precision, const double* rho_dev, double* phi_dev, double tol, int max_cg,
                     long long* iters, double* relres);

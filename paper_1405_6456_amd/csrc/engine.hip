@@ -967,11 +967,21 @@ double overlap_correction(const alofdft_system* sys, double s, std::vector<doubl
 }
 
 // ----------------------------------------------------------------- validation
+// The streaming kernels address a grid array through a raw buffer resource with 32-bit
+// byte offsets, and the CG kernels have no other form, so every padded work array (FP64,
+// or a pair of FP32 values per node) must stay below 4 GiB: cubes up to 768^3 nodes at
+// n = 6.
+void require_addressable(alofdft_ctx* c, const int n[3], int fdn) {
+  const Geom g = make_geom(n, fdn);
+  require(c, g.total * 8 < (1ll << 32), "grid too large: a padded FP64 array must stay below 4 GiB");
+}
+
 void validate(alofdft_ctx* c, const alofdft_system* s, const alofdft_params* p) {
   require(c, s && p, "null system or params");
   require(c, p->fd_half_width >= 1 && p->fd_half_width <= kMaxRadius, "fd_half_width must be in 1..8");
   require(c, std::isfinite(s->h) && s->h > 0, "h must be > 0");
   for (int a = 0; a < 3; ++a) require(c, s->n[a] >= 2 * p->fd_half_width + 1, "grid smaller than 2n+1 nodes");
+  require_addressable(c, s->n, p->fd_half_width);
   require(c, s->M >= 1 && s->R && s->Z, "need at least one atom");
   require(c, std::isfinite(s->N_elec) && s->N_elec > 0, "N must be > 0");
   require(c, p->lambda > 0 && p->gauss_width > 0 && p->r_cut > 0, "lambda, gauss_width, r_cut must be > 0");
@@ -2417,6 +2427,7 @@ int alofdft_poisson(alofdft_ctx* c, const int n[3], double h, const double origi
     require(c, bc == ALOFDFT_BC_ZERO || bc == ALOFDFT_BC_MULTIPOLE, "bad bc");
     require(c, precision == ALOFDFT_FP64 || precision == ALOFDFT_FP32_REFINED, "bad precision");
     for (int a = 0; a < 3; ++a) require(c, n[a] >= 2 * fdn + 1, "grid smaller than 2n+1 nodes");
+    require_addressable(c, n, fdn);
     (void)origin;  // the boundary expansion uses offsets from the box centre only
     const Geom g = make_geom(n, fdn);
     double* b = bufT<double>(c, "po.rho", g.total);

@@ -54,6 +54,22 @@ def test_bad_electron_count_is_refused(C, N):
     assert err.value.status == lib.INVALID_ARGUMENT
 
 
+def test_grid_beyond_the_array_limit_is_refused(C):
+    # a padded FP64 array of an 800^3 grid passes 4 GiB, past what the kernels' 32-bit
+    # buffer offsets reach: refused before anything is allocated, and the context still works
+    import paper_1405_6456_amd as lib
+
+    S = synth.single_atom(L=16.0, n=21)
+    S.grid = synth.Grid((800, 800, 800), 0.02, (0.0, 0.0, 0.0))
+    with pytest.raises(lib.AlofdftError) as err:
+        C.solve(S, lib.default_params(), None, want_fields=False)
+    assert err.value.status == lib.INVALID_ARGUMENT
+    assert "4 GiB" in str(err.value)
+    S = synth.single_atom(L=16.0, n=21)
+    out = C.solve(S, lib.default_params(), None, want_fields=False)
+    assert out["status"] == lib.OK
+
+
 def test_cancel_mid_solve_then_solve_again(C):
     import paper_1405_6456_amd as lib
 
