@@ -539,7 +539,8 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
                             stop_on_stagnation, first_poll);
   const std::string t(tag);
   // FP32 schedule 1 keeps p and A p interleaved: one 8-byte access per node for the pair
-  const bool paired = sched == 1 && sizeof(T) == 4 && 8 * g.total < (1ll << 32);
+  // (the pair array is as large as an FP64 array, which require_addressable keeps below 4 GiB)
+  const bool paired = sched == 1 && sizeof(T) == 4;
   T* r = gridbuf<T>(c, t + ".r", g);
   T* p0 = gridbuf<T>(c, t + ".p0", g);
   T* p1 = sched == 0 ? gridbuf<T>(c, t + ".p1", g) : p0;
@@ -548,15 +549,14 @@ CGResult cg_solve(alofdft_ctx* c, const Geom& g, const StencilW<T>& A, const T* 
   // first half of schedule 1 (interleaved pairs, or x made here in FP64, or neither)
   auto launch_first = [&](const CGP1Op<T>& op1, hipEvent_t ea, hipEvent_t eb) -> int {
     if constexpr (sizeof(T) == 4) {
-      if (paired) {
-        CGP1LIOp opi{op1};
-        opi.pa = pa;
-        return launch_stencil(c, g, A, opi, ea, eb);
-      }
+      CGP1LIOp opi{op1};
+      opi.pa = pa;
+      return launch_stencil(c, g, A, opi, ea, eb);
+    } else {
+      CGP1LOp<T> opl{op1};
+      opl.x = x;  // also makes the pending x += alpha p
+      return launch_stencil(c, g, A, opl, ea, eb);
     }
-    CGP1LOp<T> opl{op1};
-    opl.x = CGP1LOp<T>::XD ? x : nullptr;  // FP64: also makes the pending x += alpha p
-    return launch_stencil(c, g, A, opl, ea, eb);
   };
   const int maxsb = max_stencil_blocks(g, c->target_blocks);
   double* partsI = bufT<double>(c, t + ".partsI", (size_t)std::max(maxsb, kPointwiseBlocks) * 2);

@@ -922,8 +922,9 @@ struct CGP1Op {
 // loaded anyway, and the second half only updates r (10 array passes per iteration
 // instead of 11); alpha of iteration k - 1 comes from CGState::xa.  The launch in which
 // the solve converges has no p to form, so it only makes that last update of x (xonly,
-// op.xpass); launches queued after it stop in their prologue.  In FP32 the two extra
-// node operands cost the first half more than they save the second, so x stays there.
+// op.xpass); launches queued after it stop in their prologue.  The solves launch this op
+// in FP64 only; the FP32 first half is CGP1LIOp, which leaves x to the second half (there
+// the two extra node operands cost the first half more than they save the second).
 template <typename T>
 struct CGP1LOp : CGP1Op<T> {
   static constexpr bool NEEDC = true;

@@ -161,8 +161,7 @@ hipError_t launch_stencil_r(const LaunchCfg& lc, const Geom& g, const StencilW<T
     // against 12.7 at 109^3; FP64 53.7-58.4 against 61.5 at 185^3, 15.5 against 17.9 at
     // 109^3; 16-wave tiles were slower for both)
     if constexpr (is_cg_pipe<Op>::value) return launch_cfg2<T, R, 8, 2, 1, Op>(lc, g, W, op, nblocks, alt);
-    if constexpr (std::is_same_v<Op, CGP1LOp<float>> || std::is_same_v<Op, CGP1LOp<double>> ||
-                  std::is_same_v<Op, CGP1LIOp>)
+    if constexpr (std::is_same_v<Op, CGP1LOp<double>> || std::is_same_v<Op, CGP1LIOp>)
       return launch_cfg2<T, R, 8, 1, 1, Op>(lc, g, W, op, nblocks, alt);
     return launch_cfg2<T, R, 4, 2, 1, Op>(lc, g, W, op, nblocks, alt);
   } else {
@@ -248,7 +247,6 @@ ALOFDFT_INST(double, CGP1Op<double>)
 ALOFDFT_INST(float, CGP1Op<float>)
 ALOFDFT_INST(double, GradOp)
 ALOFDFT_INST(double, CGP1LOp<double>)
-ALOFDFT_INST(float, CGP1LOp<float>)
 ALOFDFT_INST(float, CGP1LIOp)
 ALOFDFT_INST(double, CGWInitOp<double>)
 ALOFDFT_INST(float, CGWInitOp<float>)

@@ -150,6 +150,23 @@ def test_poisson_cg_tile_variants(C, orc, schedule, tuning):
     assert np.abs(phi.cpu().numpy() - ref).max() <= 1e-8 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("tuning", [5, 6, 9, 10, 11, 14, 17, 18, 19])
+def test_poisson_fp32_refined_cg_tile_variants(C, orc, tuning):
+    # the FP32 first half (p and A p as one array of pairs) in every tile shape, inside the
+    # refined solve, reaches the oracle's solution (ragged 41x38x35 grid)
+    g = synth.Grid((41, 38, 35), 0.45, (-9.0, -8.3, -7.6))
+    rho = _gauss_rho(g, [(1.0, (0.3, -0.4, 0.2), 1.0), (-0.7, (-1.1, 0.8, -0.3), 0.9)])
+    rhs = orc.poisson_rhs(g, 6, 1, rho)
+    ref, _, _, _ = orc.poisson_cg(g, 6, rhs, tol=1e-13)
+    C.set_tuning(tuning, 0, 6)
+    try:
+        phi, its, rel = C.poisson(dev(rho), g, bc=1, precision=1, tol=1e-11)
+    finally:
+        C.set_tuning(-1, 0, 6)
+    assert rel < 1e-11
+    assert np.abs(phi.cpu().numpy() - ref).max() <= 1e-8 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("schedule", [0, 1, 2])
 def test_poisson_iteration_cap(C, schedule):
     # stopped by the cap: exactly max_cg iterations and the true relative residual of the last iterate
