@@ -365,7 +365,8 @@ int alofdft_set_tuning(alofdft_ctx* ctx, int stencil_variant, int target_blocks,
  *      A p = A r + beta A p updated in place at each node, p.Ap.  In FP64 this
  *      launch also makes x += alpha p of the previous iteration (p is loaded there
  *      anyway) and the second launch updates only r; the launch that finds the
- *      solve converged makes the last x update.
+ *      solve converged makes the last x update.  In FP32 p and A p are kept as one
+ *      array of (p, A p) pairs, one 8-byte access per node in both launches.
  *   2  one launch and one reduction per iteration, pipelined form (Chronopoulos-
  *      Gear scalars, Ghysels-Vanroose recurrences): w = A r, s = A p and z = A s
  *      are kept as vectors, the stencil is applied to the stored w (m = A w), then
