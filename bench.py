@@ -26,7 +26,8 @@ stencil (plain stencil only, then a reference copy for counter calibration), cou
 short refined Poisson solve, then the reference copy), serve (the 64-request stream of fcc
 1-3 clusters at arrival rates 0.5, 1 and 2 times the sequential FP64 capacity), relax,
 methods (augmented Lagrangian, penalty and Lagrange multiplier, and the eta0 / mu0 / kappa
-sweep), large (the 97 556-atom cluster's hot steps), --summarize-counters (writes
+sweep), large (the 97 556-atom cluster: pseudocharge, Poisson solves, one hot-path pass per
+precision, stencil), --summarize-counters (writes
 profiles/traffic.json from two counter CSVs of --mode counters).
 """
 import argparse
