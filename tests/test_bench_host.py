@@ -5,6 +5,8 @@ import os
 import subprocess
 import sys
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
@@ -24,12 +26,14 @@ def _csv(path, rows):
             f.write(f'"{k}",{c},{v}\n')
 
 
-def test_counter_summary_scales_by_the_reference_copy(tmp_path):
+@pytest.mark.parametrize("st", ["void alofdft::k_stencil2<float, 6, 4, 2, 1, alofdft::CGP1LOp<float> >(alofdft::Geom)",
+                                "void alofdft::k_stencil2<float, 6, 8, 1, 1, alofdft::CGP1LIOp, 1>(alofdft::Geom)"])
+def test_counter_summary_scales_by_the_reference_copy(tmp_path, st):
     # the copy of 256 MiB reads 131072 KiB on FETCH_SIZE (factor 2: a 128-byte read request
     # counts as 64 bytes) and 262144 KiB on WRITE_SIZE (factor 1); the CG kernels' per-dispatch
     # means are scaled by the same factor and summed over the two launches of an iteration
-    st = "void alofdft::k_stencil2<float, 6, 4, 2, 1, alofdft::CGP1LOp<float> >(alofdft::Geom)"
-    up = "void alofdft::k_cg_update<float, 256>(alofdft::Geom, alofdft::CGP2Op<float>)"
+    # (the FP32 first half with separate p and A p arrays, or as one array of pairs)
+    up = "void alofdft::k_cg_update<float, 256, true, true>(alofdft::Geom, alofdft::CGP2Op<float>)"
     fetch, write = tmp_path / "f.csv", tmp_path / "w.csv"
     _csv(fetch, [(st, "FETCH_SIZE", 1000.0), (st, "FETCH_SIZE", 1200.0), (up, "FETCH_SIZE", 700.0),
                  ("__amd_rocclr_copyBuffer", "FETCH_SIZE", 131072.0), ("tiny copyBuffer", "FETCH_SIZE", 1.0)])
