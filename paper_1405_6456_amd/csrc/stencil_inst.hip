@@ -161,6 +161,12 @@ hipError_t launch_stencil_r(const LaunchCfg& lc, const Geom& g, const StencilW<T
     // against 12.7 at 109^3; FP64 53.7-58.4 against 61.5 at 185^3, 15.5 against 17.9 at
     // 109^3; 16-wave tiles were slower for both)
     if constexpr (is_cg_pipe<Op>::value) return launch_cfg2<T, R, 8, 2, 1, Op>(lc, g, W, op, nblocks, alt);
+    // the FP32 first half (pairs of p and A p) from 250^3 over 64 x 32 tiles of 16 waves of
+    // two rows: 474^3 452 us against 495 us (185^3: 34.0 against 28.5-29.0 us)
+    if constexpr (std::is_same_v<Op, CGP1LIOp>) {
+      if ((long long)g.nx * g.ny * g.nz >= 250ll * 250 * 250)
+        return launch_cfg2<T, R, 16, 2, 1, Op>(lc, g, W, op, nblocks, alt);
+    }
     if constexpr (std::is_same_v<Op, CGP1LOp<double>> || std::is_same_v<Op, CGP1LIOp>)
       return launch_cfg2<T, R, 8, 1, 1, Op>(lc, g, W, op, nblocks, alt);
     return launch_cfg2<T, R, 4, 2, 1, Op>(lc, g, W, op, nblocks, alt);
